@@ -1,0 +1,174 @@
+/*
+ * stencil.h -- C ABI of the MI355X stencil library (libstencil.so).
+ *
+ * Repeated time-stepped updates of 3D star stencils on Cartesian lattices,
+ * after Malas et al., "Multicore-optimized wavefront diamond blocking for
+ * optimizing stencil updates" (arXiv 1410.3060):
+ *   - the five operators of Fig. 1b-1e (Sect. 2.1),
+ *   - a one-sweep-per-step scheme ("naive", Sect. 4.1),
+ *   - a temporally blocked scheme: diamond tiles along y with a wavefront
+ *     along z (Sect. 4.2-4.3 and 5.1),
+ *   - the adjoint (reverse time stepping) of the leapfrog with c(x), which
+ *     the paper does not treat: it is the transpose of the Fig. 1e recurrence.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller, who
+ *   keeps it alive until stencil_sync() returns.  The library owns only its
+ *   context and the workspace inside it.
+ * Layout (Sect. 2.1: x is the leading dimension, then y, then z).  A field is
+ *   a padded box with a boundary shell of width `halo` on all six faces.  The
+ *   pointer addresses the padded origin (x, y, z) = (-halo, -halo, -halo);
+ *   interior point (x, y, z), 0 <= x < nx etc., is element
+ *       (z + halo) * sz + (y + halo) * sy + (x + halo).
+ *   x stride is 1; sy >= nx + 2*halo; sz >= sy * (ny + 2*halo).  All fields of
+ *   one call (both time levels, every coefficient array, adjoint inputs and
+ *   outputs) share these element strides.
+ * Boundary.  The shell is read as a Dirichlet boundary and never written.
+ *   Time level t reads the shell of the buffer that holds level t in the
+ *   two-buffer scheme below; callers who want a time-independent boundary give
+ *   u[0] and u[1] the same shell (the usual case: both zero).
+ * Two-buffer time storage (Sect. 2.1: only two levels are stored and level
+ *   t+1 overwrites level t-1).  Jacobi kinds (1-3): u[0] holds level 0 on
+ *   entry and level t lives in u[t % 2].  Leapfrog kinds (4-5): u[0] holds
+ *   u_{-1}, u[1] holds u_0 and level n lives in u[(n + 1) % 2].
+ * Precision.  Lattice values are FP32.  Coefficient arrays are FP32 or BF16
+ *   (expanded exactly to FP32 in the kernels); arithmetic is FP32 with one
+ *   fixed fused-multiply-add order per kind, the same in every scheme, so the
+ *   blocked scheme reproduces the naive scheme bit for bit.  FP64 is used only
+ *   for the coefficient gradient of stencil_adjoint().
+ * Streams.  Calls are asynchronous on the HIP stream given to stencil_create()
+ *   (borrowed, not owned).  Device faults surface at the next stencil_sync().
+ * Errors.  Every argument is validated on the host before any HIP call.  A
+ *   non-zero return leaves caller memory untouched (except after
+ *   STENCIL_ERR_DEVICE) and sets a thread-local message, read with
+ *   stencil_last_error().
+ */
+#ifndef STENCIL_H
+#define STENCIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    STENCIL_OK = 0,
+    STENCIL_ERR_INVALID = 1,     /* bad argument */
+    STENCIL_ERR_UNSUPPORTED = 2, /* valid but not provided (e.g. BF16 with a constant kind) */
+    STENCIL_ERR_NOMEM = 3,       /* workspace over the tuning limit or allocation failure */
+    STENCIL_ERR_DEVICE = 4       /* HIP runtime error; message from hipGetErrorString */
+};
+
+/* Stencil operators (Fig. 1 of the paper). */
+typedef enum {
+    /* Fig. 1b, R = 1: u' = w[0]*u + w[1]*(sum of the six face neighbours). */
+    STENCIL_7PT_CONST = 1,
+    /* Fig. 1c, R = 1, K = 7 arrays: u' = sum_k W_k * u(nbr_k), neighbour order
+       centre, x-1, x+1, y-1, y+1, z-1, z+1. */
+    STENCIL_7PT_VAR = 2,
+    /* Fig. 1d, R = 4, K = 13 arrays: u' = W_0*u + sum_{r=1..4}
+       [W_{3r-2}*(x pair at r) + W_{3r-1}*(y pair) + W_{3r}*(z pair)]. */
+    STENCIL_25PT_VAR = 3,
+    /* Fig. 1e with scalar alpha (coeffs.alpha), R = 4:
+       u_{n+1} = 2 u_n - u_{n-1} + alpha * L8(u_n),
+       L8(u) = w[0]*u + sum_{r=1..4} w[r]*(x pair + y pair + z pair at r). */
+    STENCIL_25PT_WAVE = 4,
+    /* Fig. 1e with alpha a domain-sized array (K = 1), e.g. c(x) of the wave
+       equation. */
+    STENCIL_25PT_WAVE_VARC = 5
+} stencil_kind;
+
+typedef enum {
+    STENCIL_NAIVE = 0,  /* one full sweep per time step (Sect. 4.1) */
+    STENCIL_BLOCKED = 1 /* diamond tiles in y, wavefront in z (Sect. 4.2, 4.3, 5.1) */
+} stencil_scheme;
+
+typedef enum { STENCIL_F32 = 0, STENCIL_BF16 = 1 } stencil_dtype;
+
+typedef struct {
+    int32_t nx, ny, nz; /* interior sizes, each >= 0 (0 makes every call a no-op) */
+    int32_t halo;       /* boundary width, >= R of the kind (1 or 4) */
+    int64_t sy, sz;     /* element strides (see layout above) */
+    void* u[2];         /* FP32 fields, distinct, see the two-buffer convention */
+} stencil_grid;
+
+typedef struct {
+    stencil_dtype dtype; /* storage of `arrays`; BF16 only for kinds 2, 3, 5 */
+    const void* arrays;  /* K arrays for kinds 2 (K=7), 3 (K=13), 5 (K=1); unused otherwise */
+    int64_t sk;          /* element stride between arrays, >= sz * (nz + 2*halo) */
+    double w[5];         /* kind 1: w[0] centre, w[1] neighbour; kinds 4-5: L8 weights */
+    double alpha;        /* kind 4 */
+} stencil_coeffs;
+
+typedef struct {
+    int32_t dw;          /* diamond width in y for STENCIL_BLOCKED: a multiple of 2R with
+                            dw >= 4R; 0 = the library's choice */
+    int32_t xtile;       /* reserved, 0 */
+    int32_t zchunk;      /* planes per z-chunk of one workgroup (parallelism along z);
+                            0 = the library's choice */
+    int32_t ckpt_every;  /* checkpoint interval recorded by stencil_run() for kind 5;
+                            0 = no recording */
+    int64_t workspace_limit; /* bytes the context may allocate; 0 = no limit */
+} stencil_tuning;
+
+typedef struct stencil_ctx stencil_ctx;
+
+/* Create a context for one scheme.  `tuning` may be NULL (all zero).
+   `hip_stream` is a hipStream_t (NULL = the null stream), borrowed.  No HIP
+   call is made here: the context binds to the device that is current at its
+   first device call (stencil_run / stencil_adjoint with work to do). */
+int stencil_create(stencil_ctx** out, stencil_scheme scheme, const stencil_tuning* tuning,
+                   void* hip_stream);
+
+/* Advance `nt` >= 0 time steps in place (Fig. 1b-1e, two-buffer storage as
+   above).  On return *result_slot (if not NULL) is the index of u[] that holds
+   level nt: nt % 2 for kinds 1-3, (nt + 1) % 2 for kinds 4-5 (the other slot
+   then holds u_{nt-1}).  nt = 0 is a no-op.  For kind 5 with ckpt_every > 0
+   the context records (u_{n-1}, u_n) for n = 0, k, 2k, ... < nt (k =
+   ckpt_every) for a later stencil_adjoint(); the recording is replaced by the
+   next recording run. */
+int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
+                const stencil_coeffs* coeffs, int64_t nt, int* result_slot);
+
+/* Reverse time stepping for kind 5 (STENCIL_25PT_WAVE_VARC).  With
+   M = 2I + diag(c) L8 the forward map is u_{n+1} = M u_n - u_{n-1}; for a
+   loss with seed lambda_nt = dJ/du_nt the adjoint recurrence is
+       lambda_n = 2 lambda_{n+1} - lambda_{n+2} + L8(c * lambda_{n+1}),
+   lambda_{nt+1} = 0, and the outputs are
+       grad_u0  = dJ/du_0    = lambda_0,
+       grad_um1 = dJ/du_{-1} = -lambda_1,
+       grad_c   = dJ/dc      = sum_{n=0}^{nt-1} lambda_{n+1} * L8(u_n)   (FP64).
+   Forward states are rebuilt from the context's recording when it matches
+   (same sizes, strides, coefficient pointer and nt; made by stencil_run with
+   ckpt_every > 0); otherwise grid->u[0], grid->u[1] must hold the INITIAL
+   (u_{-1}, u_0) and the forward pass is recomputed with checkpoints first.
+   seed, grad_u0, grad_um1 are FP32 and grad_c FP64 padded fields with the
+   grid's strides; only their interiors are read or written.  grad_c is
+   overwritten (not accumulated).  The context allocates ~ (ckpt_every + 4)
+   fields of workspace plus one FP64 field. */
+int stencil_adjoint(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
+                    const stencil_coeffs* coeffs, int64_t nt, const float* seed,
+                    float* grad_u0, float* grad_um1, double* grad_c);
+
+/* Wait for all work of this context; reports asynchronous device errors. */
+int stencil_sync(stencil_ctx* ctx);
+
+/* Release the context and its workspace (waits for its stream first). */
+void stencil_destroy(stencil_ctx* ctx);
+
+/* Message of the last non-zero return on this thread ("" if none). */
+const char* stencil_last_error(void);
+
+/* Diamond geometry the blocked scheme uses for (kind, dw, ny, nt), for tests
+   and tuning: fills up to `cap` rows of {row, t0, n_diamonds, first_centre}
+   and returns the number of diamond rows, or -1 on a bad argument. */
+int stencil_plan_rows(stencil_kind kind, int32_t dw, int32_t ny, int64_t nt, int64_t* out,
+                      int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_H */

@@ -65,6 +65,9 @@ def _load():
     lib.oracle_adjoint_wave_varc.argtypes = [i64, i64, i64, i64, D, D, D, D, i64, D,
                                              D, D, D, ctypes.c_int]
     lib.oracle_adjoint_wave_varc.restype = ctypes.c_int
+    lib.oracle_step_points.argtypes = [ctypes.c_int, i64, i64, i64, i64, D, D, D, D,
+                                       ctypes.c_double, i64, ctypes.POINTER(i64), D]
+    lib.oracle_step_points.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -117,6 +120,47 @@ def run(kind, u, h, nt, *, u_prev=None, coef=None, w=(0.0,) * 5, alpha=0.0,
     if timing is not None:
         timing.append(secs.value)
     return (up, u) if kind >= KIND_WAVE else u
+
+
+def step_points(kind, u, h, pts, *, u_prev=None, coef=None, w=(0.0,) * 5, alpha=0.0):
+    """One update evaluated at interior points pts (an (n, 3) array of x, y, z).
+
+    Works on arrays of any size: only the neighbourhoods of the points are read.
+    ``u``, ``u_prev`` and ``coef`` may be float32 arrays; they are read as
+    float64 one point at a time via a gathered copy of the needed values.
+    """
+    lib = _load()
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    n = pts.shape[0]
+    R = RADIUS[kind]
+    nx, ny, nz = _dims(u, h)
+    # gather the (2R+1)^3 neighbourhood boxes into a small padded array per
+    # point so that huge float32 fields need not be converted whole
+    side = 2 * R + 1
+    out = np.empty(n, dtype=np.float64)
+    K = NCOEF[kind]
+    wv = np.zeros(5, dtype=np.float64)
+    wv[: len(w)] = np.asarray(w, dtype=np.float64)
+    offs = np.arange(-R, R + 1)
+    for i in range(n):
+        x, y, z = (int(v) for v in pts[i])
+        zs, ys, xs = z + h + offs, y + h + offs, x + h + offs
+        sub = np.ascontiguousarray(u[np.ix_(zs, ys, xs)], dtype=np.float64)
+        sp_ = None
+        if kind >= KIND_WAVE:
+            sp_ = np.ascontiguousarray(u_prev[np.ix_(zs, ys, xs)], dtype=np.float64)
+        cf = None
+        if K:
+            cf = np.ascontiguousarray(coef[(slice(None),) + np.ix_(zs, ys, xs)], dtype=np.float64)
+        one = np.array([[0, 0, 0]], dtype=np.int64)
+        res = np.empty(1, dtype=np.float64)
+        rc = lib.oracle_step_points(kind, 1, 1, 1, R, _p(sp_), _p(sub), _p(cf), _p(wv),
+                                    float(alpha), 1,
+                                    one.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(res))
+        if rc != 0:
+            raise ValueError("oracle_step_points rejected its arguments")
+        out[i] = res[0]
+    return out
 
 
 def adjoint_wave_varc(um1, u0, c, h, nt, seed, w, nthreads=0):

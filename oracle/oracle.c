@@ -307,3 +307,56 @@ int oracle_adjoint_wave_varc(int64_t nx, int64_t ny, int64_t nz, int64_t h,
     free(hist); free(lam); free(cl);
     return 0;
 }
+
+/*
+ * One update (Fig. 1b-1e) evaluated at a list of interior points, for
+ * checking single sweeps of very large grids on sampled outputs.  pts holds
+ * npts triples (x, y, z); out[i] receives the new value at point i (for the
+ * leapfrog kinds: 2 u - u_prev + alpha L8(u)).  Returns 0 or -1.
+ */
+int oracle_step_points(int kind, int64_t nx, int64_t ny, int64_t nz, int64_t h,
+                       const double* u_prev, const double* u, const double* coef,
+                       const double* w, double alpha, int64_t npts, const int64_t* pts,
+                       double* out) {
+    if (kind < OK_7C || kind > OK_WAVE_VARC || h < radius_of(kind) || !u || !w || !pts || !out)
+        return -1;
+    if (ncoef_of(kind) > 0 && !coef) return -1;
+    if (kind >= OK_WAVE && !u_prev) return -1;
+    box b = mkbox(nx, ny, nz, h);
+    const int64_t n = box_size(&b);
+    for (int64_t i = 0; i < npts; ++i) {
+        const int64_t x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+        if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz) return -1;
+        const int64_t p = at(&b, x, y, z);
+        double v;
+        if (kind == OK_7C) {
+            v = w[0] * u[p]
+              + w[1] * (u[at(&b, x - 1, y, z)] + u[at(&b, x + 1, y, z)])
+              + w[1] * (u[at(&b, x, y - 1, z)] + u[at(&b, x, y + 1, z)])
+              + w[1] * (u[at(&b, x, y, z - 1)] + u[at(&b, x, y, z + 1)]);
+        } else if (kind == OK_7V) {
+            const double* W = coef;
+            v = W[0 * n + p] * u[p]
+              + W[1 * n + p] * u[at(&b, x - 1, y, z)]
+              + W[2 * n + p] * u[at(&b, x + 1, y, z)]
+              + W[3 * n + p] * u[at(&b, x, y - 1, z)]
+              + W[4 * n + p] * u[at(&b, x, y + 1, z)]
+              + W[5 * n + p] * u[at(&b, x, y, z - 1)]
+              + W[6 * n + p] * u[at(&b, x, y, z + 1)];
+        } else if (kind == OK_25V) {
+            const double* W = coef;
+            v = W[0 * n + p] * u[p];
+            for (int r = 1; r <= 4; ++r) {
+                const int64_t kx = 3 * (r - 1) + 1, ky = kx + 1, kz = kx + 2;
+                v += W[kx * n + p] * (u[at(&b, x - r, y, z)] + u[at(&b, x + r, y, z)]);
+                v += W[ky * n + p] * (u[at(&b, x, y - r, z)] + u[at(&b, x, y + r, z)]);
+                v += W[kz * n + p] * (u[at(&b, x, y, z - r)] + u[at(&b, x, y, z + r)]);
+            }
+        } else {
+            const double a = (kind == OK_WAVE_VARC) ? coef[p] : alpha;
+            v = 2.0 * u[p] - u_prev[p] + a * lap8(&b, u, w, x, y, z);
+        }
+        out[i] = v;
+    }
+    return 0;
+}

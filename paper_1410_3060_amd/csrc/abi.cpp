@@ -1,0 +1,590 @@
+// C ABI of libstencil.so: argument validation, contexts, workspace and the
+// host-side time loop.  Every argument is checked before the first HIP call,
+// so every error path can be exercised on a machine without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "adjoint.h"
+#include "blocked.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int dev_fail(hipError_t e, const char* what) {
+    return fail(STENCIL_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int kind_radius(int kind) { return (kind == 1 || kind == 2) ? 1 : 4; }
+int kind_ncoef(int kind) {
+    switch (kind) {
+    case 2: return 7;
+    case 3: return 13;
+    case 5: return 1;
+    default: return 0;
+    }
+}
+bool kind_leapfrog(int kind) { return kind == 4 || kind == 5; }
+
+}  // namespace
+
+struct stencil_ctx {
+    stencil_scheme scheme;
+    stencil_tuning tuning;
+    hipStream_t stream;
+    int device;
+    // workspace: a list of device allocations owned by the context
+    std::vector<std::pair<void*, size_t>> bufs;
+    size_t ws_bytes = 0;
+    // blocked scheme frontier buffers (two pairs of fields)
+    void* frontier = nullptr;
+    size_t frontier_bytes = 0;
+    // checkpoints recorded by stencil_run for stencil_adjoint (kind 5)
+    struct recording {
+        bool valid = false;
+        int nx = 0, ny = 0, nz = 0, halo = 0;
+        int64_t sy = 0, sz = 0, nt = 0;
+        int every = 0;            // checkpoint interval k
+        const void* coef = nullptr;
+        int dtype = 0;
+        float* buf = nullptr;     // 2 * n fields: (u_{qk-1}, u_{qk}) for q = 0 .. n-1
+        size_t span = 0;          // elements per field
+        int n = 0;
+    } rec;
+};
+
+namespace {
+
+// Allocate (or reuse) a device workspace region tracked by the context.
+int ws_alloc(stencil_ctx* ctx, size_t bytes, void** out) {
+    if (ctx->tuning.workspace_limit > 0 &&
+        ctx->ws_bytes + bytes > (size_t)ctx->tuning.workspace_limit)
+        return fail(STENCIL_ERR_NOMEM,
+                    "workspace of %zu bytes exceeds the tuning limit of %lld bytes",
+                    ctx->ws_bytes + bytes, (long long)ctx->tuning.workspace_limit);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(STENCIL_ERR_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    ctx->bufs.push_back({p, bytes});
+    ctx->ws_bytes += bytes;
+    *out = p;
+    return STENCIL_OK;
+}
+
+void ws_free(stencil_ctx* ctx, void* p) {
+    for (size_t i = 0; i < ctx->bufs.size(); ++i)
+        if (ctx->bufs[i].first == p) {
+            (void)hipFree(p);
+            ctx->ws_bytes -= ctx->bufs[i].second;
+            ctx->bufs.erase(ctx->bufs.begin() + (long)i);
+            return;
+        }
+}
+
+// Elements spanned by one padded field (from the origin to the last element).
+int64_t field_span(const stencil_grid* g) {
+    const int64_t h = g->halo;
+    return (g->nz + 2 * h - 1) * g->sz + (g->ny + 2 * h - 1) * g->sy + (g->nx + 2 * h);
+}
+
+int validate_grid(int kind, const stencil_grid* g) {
+    if (!g) return fail(STENCIL_ERR_INVALID, "grid is NULL");
+    if (g->nx < 0 || g->ny < 0 || g->nz < 0)
+        return fail(STENCIL_ERR_INVALID, "negative grid size (%d, %d, %d)", g->nx, g->ny, g->nz);
+    const int R = kind_radius(kind);
+    if (g->halo < R)
+        return fail(STENCIL_ERR_INVALID, "halo %d is smaller than the stencil radius %d", g->halo, R);
+    if (g->halo > 64) return fail(STENCIL_ERR_INVALID, "halo %d is larger than 64", g->halo);
+    const int64_t px = (int64_t)g->nx + 2 * g->halo, py = (int64_t)g->ny + 2 * g->halo;
+    if (g->sy < px)
+        return fail(STENCIL_ERR_INVALID, "row stride sy=%lld < nx + 2*halo = %lld",
+                    (long long)g->sy, (long long)px);
+    if (g->sz < g->sy * py)
+        return fail(STENCIL_ERR_INVALID, "plane stride sz=%lld < sy*(ny + 2*halo) = %lld",
+                    (long long)g->sz, (long long)(g->sy * py));
+    if ((int64_t)g->nx + 2 * g->halo > (1 << 30) || (int64_t)g->ny + 2 * g->halo > (1 << 30) ||
+        (int64_t)g->nz + 2 * g->halo > (1 << 30))
+        return fail(STENCIL_ERR_INVALID, "grid dimension too large");
+    if (!g->u[0] || !g->u[1]) return fail(STENCIL_ERR_INVALID, "grid field pointer is NULL");
+    if (g->u[0] == g->u[1]) return fail(STENCIL_ERR_INVALID, "u[0] and u[1] must be distinct");
+    return STENCIL_OK;
+}
+
+int validate_coeffs(int kind, const stencil_grid* g, const stencil_coeffs* c) {
+    if (!c) return fail(STENCIL_ERR_INVALID, "coeffs is NULL");
+    if (c->dtype != STENCIL_F32 && c->dtype != STENCIL_BF16)
+        return fail(STENCIL_ERR_INVALID, "unknown coefficient dtype %d", (int)c->dtype);
+    const int K = kind_ncoef(kind);
+    if (K == 0) {
+        if (c->dtype != STENCIL_F32)
+            return fail(STENCIL_ERR_UNSUPPORTED,
+                        "BF16 coefficient storage needs a variable-coefficient kind (2, 3, 5)");
+    } else {
+        if (!c->arrays) return fail(STENCIL_ERR_INVALID, "kind %d needs %d coefficient arrays", kind, K);
+        if (K > 1 && c->sk < field_span(g))
+            return fail(STENCIL_ERR_INVALID, "coefficient stride sk=%lld overlaps the arrays (need >= %lld)",
+                        (long long)c->sk, (long long)field_span(g));
+    }
+    for (int i = 0; i < 5; ++i)
+        if (!std::isfinite(c->w[i])) return fail(STENCIL_ERR_INVALID, "w[%d] is not finite", i);
+    if (!std::isfinite(c->alpha)) return fail(STENCIL_ERR_INVALID, "alpha is not finite");
+    return STENCIL_OK;
+}
+
+stn::dims to_dims(const stencil_grid* g) {
+    stn::dims d;
+    d.nx = g->nx; d.ny = g->ny; d.nz = g->nz; d.h = g->halo; d.sy = g->sy; d.sz = g->sz;
+    return d;
+}
+
+stn::host_weights to_weights(const stencil_coeffs* c) {
+    stn::host_weights w;
+    for (int i = 0; i < 5; ++i) w.w[i] = (float)c->w[i];
+    w.alpha = (float)c->alpha;
+    return w;
+}
+
+bool empty(const stencil_grid* g) { return g->nx == 0 || g->ny == 0 || g->nz == 0; }
+
+// The context binds to the device that is current at its first device call.
+int set_device(stencil_ctx* ctx) {
+    if (ctx->device < 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return dev_fail(e, "hipGetDevice");
+        ctx->device = dev;
+        return STENCIL_OK;
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    return e == hipSuccess ? STENCIL_OK : dev_fail(e, "hipSetDevice");
+}
+
+// Naive time loop: nt launches, two-buffer storage.
+int run_naive(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
+              int64_t nt) {
+    const stn::dims d = to_dims(g);
+    const stn::host_weights w = to_weights(c);
+    const bool bf16 = c->dtype == STENCIL_BF16;
+    float* u0 = static_cast<float*>(g->u[0]);
+    float* u1 = static_cast<float*>(g->u[1]);
+    for (int64_t t = 0; t < nt; ++t) {
+        hipError_t e;
+        if (kind_leapfrog(kind)) {
+            // level t lives in u[(t+1)%2]; level t+1 overwrites level t-1
+            float* cur = (t % 2 == 0) ? u1 : u0;
+            float* old = (t % 2 == 0) ? u0 : u1;
+            e = stn::launch_naive_step(kind, bf16, cur, old, old, c->arrays, c->sk, d, w,
+                                       ctx->tuning.zchunk, ctx->stream);
+        } else {
+            const float* cur = (t % 2 == 0) ? u0 : u1;
+            float* nxt = (t % 2 == 0) ? u1 : u0;
+            e = stn::launch_naive_step(kind, bf16, cur, nullptr, nxt, c->arrays, c->sk, d, w,
+                                       ctx->tuning.zchunk, ctx->stream);
+        }
+        if (e != hipSuccess) return dev_fail(e, "naive step launch");
+    }
+    return STENCIL_OK;
+}
+
+
+// Device workspace for the blocked scheme's second frontier pair.
+int ensure_frontier(stencil_ctx* ctx, size_t bytes) {
+    if (ctx->frontier && ctx->frontier_bytes >= bytes) return STENCIL_OK;
+    if (ctx->frontier) {
+        ws_free(ctx, ctx->frontier);
+        ctx->frontier = nullptr;
+        ctx->frontier_bytes = 0;
+    }
+    void* p = nullptr;
+    int rc = ws_alloc(ctx, bytes, &p);
+    if (rc) return rc;
+    ctx->frontier = p;
+    ctx->frontier_bytes = bytes;
+    return STENCIL_OK;
+}
+
+// Blocked time loop (diamond rows of plan.h, one launch per row).  The
+// frontier pair alternates between the caller's buffers and a workspace pair;
+// when the number of rows is odd the initial state is first copied to the
+// workspace so that the last row writes the caller's buffers, with level nt in
+// the slot the two-buffer convention prescribes.
+int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
+                int64_t nt) {
+    const int R = kind_radius(kind);
+    const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
+    if (!stn::blocked_supported(kind, dw))
+        return fail(STENCIL_ERR_UNSUPPORTED, "blocked scheme: dw=%d is not provided for kind %d", dw,
+                    kind);
+    const int H = dw / (2 * R);
+    const int L = 2 * H - 1;
+    // the kernel addresses a tile's columns with 32-bit offsets
+    if ((int64_t)(dw + 2 * R) * g->sy + 256 > INT32_MAX)
+        return fail(STENCIL_ERR_UNSUPPORTED, "blocked scheme: row stride sy=%lld too large",
+                    (long long)g->sy);
+    const stn::dims d = to_dims(g);
+    const stn::diamond_plan plan = stn::make_plan(R, dw, g->ny, nt);
+    const size_t span = (size_t)field_span(g);
+    const size_t fbytes = span * sizeof(float);
+    int rc = ensure_frontier(ctx, 2 * fbytes);
+    if (rc) return rc;
+    float* w0 = static_cast<float*>(ctx->frontier);
+    float* w1 = w0 + span;
+    float* u0 = static_cast<float*>(g->u[0]);
+    float* u1 = static_cast<float*>(g->u[1]);
+    const bool lf = kind_leapfrog(kind);
+    const int slot = lf ? (int)((nt + 1) % 2) : (int)(nt % 2);
+    float* fin_top = slot ? u1 : u0;
+    float* fin_sub = slot ? u0 : u1;
+    const float* rt = lf ? u1 : u0;  // level 0
+    const float* rs = lf ? u0 : u1;  // level -1 (leapfrog) / unused (Jacobi)
+    bool reading_caller = true;
+    if (plan.rows.size() % 2 == 1) {
+        hipError_t e = hipMemcpyAsync(w0, rt, fbytes, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess && lf)
+            e = hipMemcpyAsync(w1, rs, fbytes, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) return dev_fail(e, "frontier copy");
+        rt = w0;
+        rs = w1;
+        reading_caller = false;
+    }
+    const int xomax = stn::blocked_max_xo(kind, dw);
+    const int gx = (g->nx + xomax - 1) / xomax;
+    const int xo = (g->nx + gx - 1) / gx;
+    const bool bf16 = c->dtype == STENCIL_BF16;
+    for (const stn::diamond_row& row : plan.rows) {
+        stn::blocked_row_args a;
+        a.ftop_o = rt;
+        a.fsub_o = rs;
+        a.ftop_n = reading_caller ? w0 : fin_top;
+        a.fsub_n = reading_caller ? w1 : fin_sub;
+        a.hb0 = u0;
+        a.hb1 = u1;
+        a.coef = c->arrays;
+        a.sk = c->sk;
+        a.d = d;
+        a.wt = to_weights(c);
+        a.t0 = row.t0;
+        a.nt = nt;
+        a.first_centre = row.first_centre;
+        a.n_diamonds = row.n_diamonds;
+        a.dw = dw;
+        a.xo = xo;
+        a.gx = gx;
+        int zc = ctx->tuning.zchunk;
+        if (zc <= 0) {
+            // about two workgroups per CU, chunks no thinner than 2RL planes
+            const long long per = (long long)row.n_diamonds * gx;
+            long long gz = (512 + per - 1) / per;
+            const long long zmin = std::max(8, 2 * R * L);
+            gz = std::max(1LL, std::min(gz, (long long)g->nz / zmin));
+            zc = (int)((g->nz + gz - 1) / gz);
+        }
+        a.zchunk = zc;
+        a.gz = (g->nz + zc - 1) / zc;
+        if ((long long)a.n_diamonds * a.gx * a.gz > 0x7fffffffLL)
+            return fail(STENCIL_ERR_INVALID, "grid too large for one launch");
+        hipError_t e = stn::launch_blocked_row(kind, bf16, a, ctx->stream);
+        if (e != hipSuccess) return dev_fail(e, "blocked row launch");
+        rt = a.ftop_n;
+        rs = a.fsub_n;
+        reading_caller = !reading_caller;
+    }
+    return STENCIL_OK;
+}
+
+// Forward run in segments of k steps, copying (u_{t-1}, u_t) into checkpoint q
+// before segment q (t = q k).  A segment runs on a grid whose u[0], u[1] are
+// the buffers holding u_{t-1}, u_t, so the two-buffer convention (and with it
+// the boundary shell read at each level) is the same as in one long run.
+int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
+                 int64_t nt, int k, stencil_ctx::recording* rec) {
+    const size_t span = (size_t)field_span(g);
+    const int n = (int)((nt + k - 1) / k);
+    const size_t need = 2 * (size_t)n * span * sizeof(float);
+    if (!rec->buf || rec->span * 2 * (size_t)rec->n * sizeof(float) < need) {
+        if (rec->buf) ws_free(ctx, rec->buf);
+        rec->buf = nullptr;
+        rec->valid = false;
+        void* p = nullptr;
+        int rc = ws_alloc(ctx, need, &p);
+        if (rc) return rc;
+        rec->buf = static_cast<float*>(p);
+    }
+    rec->valid = false;
+    rec->span = span;
+    rec->n = n;
+    for (int q = 0; q < n; ++q) {
+        const int64_t t = (int64_t)q * k;
+        const int64_t steps = std::min<int64_t>(k, nt - t);
+        stencil_grid sub = *g;
+        sub.u[0] = g->u[t % 2];        // holds u_{t-1}
+        sub.u[1] = g->u[(t + 1) % 2];  // holds u_t
+        hipError_t e = hipMemcpyAsync(rec->buf + (2 * (size_t)q) * span, sub.u[0],
+                                      span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(rec->buf + (2 * (size_t)q + 1) * span, sub.u[1],
+                               span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) return dev_fail(e, "checkpoint copy");
+        const int rc = ctx->scheme == STENCIL_NAIVE ? run_naive(ctx, kind, &sub, c, steps)
+                                                    : run_blocked(ctx, kind, &sub, c, steps);
+        if (rc) return rc;
+    }
+    rec->valid = true;
+    rec->nx = g->nx; rec->ny = g->ny; rec->nz = g->nz; rec->halo = g->halo;
+    rec->sy = g->sy; rec->sz = g->sz; rec->nt = nt; rec->every = k;
+    rec->coef = c->arrays;
+    rec->dtype = (int)c->dtype;
+    return STENCIL_OK;
+}
+
+bool recording_matches(const stencil_ctx::recording& r, const stencil_grid* g,
+                       const stencil_coeffs* c, int64_t nt) {
+    return r.valid && r.nx == g->nx && r.ny == g->ny && r.nz == g->nz && r.halo == g->halo &&
+           r.sy == g->sy && r.sz == g->sz && r.nt == nt && r.coef == c->arrays &&
+           r.dtype == (int)c->dtype;
+}
+
+int default_ckpt(int64_t nt) {
+    const int k = (int)std::lround(std::sqrt((double)nt));
+    return k < 1 ? 1 : k;
+}
+
+// Reverse time stepping of kind 5 from the recorded checkpoints: segments in
+// reverse order; each restores (u_{a-1}, u_a), recomputes u_{a+1} .. u_{b-1}
+// with the naive step (bit-identical to the forward), then runs the reverse
+// steps s = b-1 .. a.
+int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c, int64_t nt,
+                const float* seed, float* g_u0, float* g_um1, double* g_c) {
+    const stn::dims d = to_dims(g);
+    const hipStream_t st = ctx->stream;
+    const bool bf16 = c->dtype == STENCIL_BF16;
+    hipError_t e;
+    if (nt == 0) {
+        e = stn::launch_scale_copy(g_u0, seed, 1.0f, d, st);
+        if (e == hipSuccess) e = stn::launch_zero_f32(g_um1, d, st);
+        if (e == hipSuccess) e = stn::launch_zero_f64(g_c, d, st);
+        return e == hipSuccess ? STENCIL_OK : dev_fail(e, "adjoint (nt = 0)");
+    }
+    stencil_ctx::recording& rec = ctx->rec;
+    const size_t span = (size_t)field_span(g);
+    int rc;
+    if (!recording_matches(rec, g, c, nt)) {
+        // no usable recording: rerun the forward from the initial state held by
+        // the caller's buffers, on workspace copies
+        void* p = nullptr;
+        rc = ws_alloc(ctx, 2 * span * sizeof(float), &p);
+        if (rc) return rc;
+        float* w = static_cast<float*>(p);
+        e = hipMemcpyAsync(w, g->u[0], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(w + span, g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return dev_fail(e, "adjoint forward copy");
+        stencil_grid wg = *g;
+        wg.u[0] = w;
+        wg.u[1] = w + span;
+        const int k = ctx->tuning.ckpt_every > 0 ? ctx->tuning.ckpt_every : default_ckpt(nt);
+        rc = run_recorded(ctx, 5, &wg, c, nt, k, &rec);
+        // the recording describes the caller's grid (same sizes and strides)
+        e = hipStreamSynchronize(st);
+        ws_free(ctx, p);
+        if (rc) return rc;
+        if (e != hipSuccess) return dev_fail(e, "adjoint forward");
+    }
+    const int k = rec.every;
+    // workspace: k + 1 segment slots and two lambda fields
+    void* p = nullptr;
+    rc = ws_alloc(ctx, (size_t)(k + 3) * span * sizeof(float), &p);
+    if (rc) return rc;
+    float* slots = static_cast<float*>(p);
+    float* lam_a = slots + (size_t)(k + 1) * span;
+    float* lam_b = lam_a + span;
+    auto slot = [&](int i) { return slots + (size_t)i * span; };
+    // the boundary shell is taken as time independent: every slot gets the
+    // shell of the buffer holding level 0 (its interior is overwritten)
+    e = hipSuccess;
+    for (int i = 0; i <= k && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(slot(i), g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = stn::launch_zero_span(lam_a, 2 * span, st);
+    if (e == hipSuccess) e = stn::launch_scale_copy(lam_a, seed, 1.0f, d, st);
+    if (e == hipSuccess) e = stn::launch_zero_f64(g_c, d, st);
+    if (e != hipSuccess) {
+        ws_free(ctx, p);
+        return dev_fail(e, "adjoint setup");
+    }
+    float* cur = lam_a;  // lambda_{s+1}
+    float* nxt = lam_b;  // lambda_{s+2}, becomes lambda_s
+    const stn::host_weights wt = to_weights(c);
+    const double* w = c->w;
+    for (int q = rec.n - 1; q >= 0 && e == hipSuccess; --q) {
+        const int64_t a = (int64_t)q * k;
+        const int64_t b = std::min<int64_t>(a + k, nt);
+        e = hipMemcpyAsync(slot(0), rec.buf + (2 * (size_t)q) * span, span * sizeof(float),
+                           hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(slot(1), rec.buf + (2 * (size_t)q + 1) * span, span * sizeof(float),
+                               hipMemcpyDeviceToDevice, st);
+        // slot i holds u_{a-1+i}
+        for (int64_t i = 1; i + a < b && e == hipSuccess; ++i)
+            e = stn::launch_naive_step(5, bf16, slot((int)i), slot((int)i - 1), slot((int)i + 1),
+                                       c->arrays, c->sk, d, wt, 0, st);
+        for (int64_t s = b - 1; s >= a && e == hipSuccess; --s) {
+            e = stn::launch_adjoint_step(bf16, cur, nxt, c->arrays, slot((int)(s - a + 1)), g_c, d,
+                                         w, 0, st);
+            std::swap(cur, nxt);
+        }
+    }
+    if (e == hipSuccess) e = stn::launch_scale_copy(g_u0, cur, 1.0f, d, st);
+    if (e == hipSuccess) e = stn::launch_scale_copy(g_um1, nxt, -1.0f, d, st);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        ws_free(ctx, p);
+        return dev_fail(e, "adjoint");
+    }
+    e = hipStreamSynchronize(st);
+    ws_free(ctx, p);
+    return e == hipSuccess ? STENCIL_OK : dev_fail(e, "adjoint");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stencil_last_error(void) { return g_err.c_str(); }
+
+int stencil_create(stencil_ctx** out, stencil_scheme scheme, const stencil_tuning* tuning,
+                   void* hip_stream) {
+    if (!out) return fail(STENCIL_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (scheme != STENCIL_NAIVE && scheme != STENCIL_BLOCKED)
+        return fail(STENCIL_ERR_INVALID, "unknown scheme %d", (int)scheme);
+    stencil_tuning t{};
+    if (tuning) t = *tuning;
+    if (t.dw < 0 || t.zchunk < 0 || t.ckpt_every < 0 || t.workspace_limit < 0 || t.xtile < 0)
+        return fail(STENCIL_ERR_INVALID, "negative tuning value");
+    if (t.dw != 0 && (t.dw % 2 != 0 || t.dw < 4))
+        return fail(STENCIL_ERR_INVALID, "dw=%d must be even and >= 4", t.dw);
+    stencil_ctx* ctx = new (std::nothrow) stencil_ctx();
+    if (!ctx) return fail(STENCIL_ERR_NOMEM, "context allocation failed");
+    ctx->scheme = scheme;
+    ctx->tuning = t;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->device = -1;  // bound at the first device call
+    *out = ctx;
+    return STENCIL_OK;
+}
+
+int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
+                const stencil_coeffs* coeffs, int64_t nt, int* result_slot) {
+    if (!ctx) return fail(STENCIL_ERR_INVALID, "ctx is NULL");
+    const int k = (int)kind;
+    if (k < 1 || k > 5) return fail(STENCIL_ERR_INVALID, "unknown stencil kind %d", k);
+    int rc = validate_grid(k, grid);
+    if (rc) return rc;
+    rc = validate_coeffs(k, grid, coeffs);
+    if (rc) return rc;
+    if (nt < 0) return fail(STENCIL_ERR_INVALID, "nt=%lld is negative", (long long)nt);
+    if (ctx->scheme == STENCIL_BLOCKED && ctx->tuning.dw != 0 &&
+        ctx->tuning.dw % (2 * kind_radius(k)) != 0)
+        return fail(STENCIL_ERR_INVALID, "dw=%d is not a multiple of 2R=%d", ctx->tuning.dw,
+                    2 * kind_radius(k));
+    if (ctx->tuning.ckpt_every > 0 && k != 5)
+        return fail(STENCIL_ERR_UNSUPPORTED, "checkpoint recording is provided for kind 5 only");
+    const int slot = kind_leapfrog(k) ? (int)((nt + 1) % 2) : (int)(nt % 2);
+    if (nt == 0 || empty(grid)) {
+        if (result_slot) *result_slot = slot;
+        return STENCIL_OK;
+    }
+    rc = set_device(ctx);
+    if (rc) return rc;
+    if (ctx->tuning.ckpt_every > 0) {
+        rc = run_recorded(ctx, k, grid, coeffs, nt, ctx->tuning.ckpt_every, &ctx->rec);
+    } else if (ctx->scheme == STENCIL_NAIVE) {
+        rc = run_naive(ctx, k, grid, coeffs, nt);
+    } else {
+        rc = run_blocked(ctx, k, grid, coeffs, nt);
+    }
+    if (rc) return rc;
+    if (result_slot) *result_slot = slot;
+    return STENCIL_OK;
+}
+
+int stencil_adjoint(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
+                    const stencil_coeffs* coeffs, int64_t nt, const float* seed, float* grad_u0,
+                    float* grad_um1, double* grad_c) {
+    if (!ctx) return fail(STENCIL_ERR_INVALID, "ctx is NULL");
+    if ((int)kind != 5)
+        return fail(STENCIL_ERR_UNSUPPORTED, "the adjoint is provided for kind 5 (25PT_WAVE_VARC)");
+    int rc = validate_grid(5, grid);
+    if (rc) return rc;
+    rc = validate_coeffs(5, grid, coeffs);
+    if (rc) return rc;
+    if (nt < 0) return fail(STENCIL_ERR_INVALID, "nt=%lld is negative", (long long)nt);
+    if (!seed || !grad_u0 || !grad_um1 || !grad_c)
+        return fail(STENCIL_ERR_INVALID, "adjoint field pointer is NULL");
+    if (empty(grid)) return STENCIL_OK;
+    rc = set_device(ctx);
+    if (rc) return rc;
+    return run_adjoint(ctx, grid, coeffs, nt, seed, grad_u0, grad_um1, grad_c);
+}
+
+int stencil_sync(stencil_ctx* ctx) {
+    if (!ctx) return fail(STENCIL_ERR_INVALID, "ctx is NULL");
+    if (ctx->device < 0) return STENCIL_OK;  // nothing was ever launched
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
+    return STENCIL_OK;
+}
+
+void stencil_destroy(stencil_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->device >= 0 && hipSetDevice(ctx->device) == hipSuccess) {
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto& b : ctx->bufs) (void)hipFree(b.first);
+    }
+    delete ctx;
+}
+
+int stencil_plan_rows(stencil_kind kind, int32_t dw, int32_t ny, int64_t nt, int64_t* out,
+                      int32_t cap) {
+    const int k = (int)kind;
+    if (k < 1 || k > 5 || ny < 0 || nt < 0 || cap < 0 || (cap > 0 && !out)) return -1;
+    const int R = kind_radius(k);
+    if (dw % (2 * R) != 0 || dw < 4 * R) return -1;
+    stn::diamond_plan p = stn::make_plan(R, dw, ny, nt);
+    const int n = (int)p.rows.size();
+    for (int i = 0; i < n && i < cap; ++i) {
+        out[4 * i + 0] = p.rows[i].r;
+        out[4 * i + 1] = p.rows[i].t0;
+        out[4 * i + 2] = p.rows[i].n_diamonds;
+        out[4 * i + 3] = p.rows[i].first_centre;
+    }
+    return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,37 @@
+// Host-side interface of the blocked (diamond/wavefront) row kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace stn {
+
+// One row of diamonds: reads the old frontier pair, writes the new one.
+struct blocked_row_args {
+    const float* ftop_o;  // old frontier: newest level per point
+    const float* fsub_o;  // old frontier: the level below it
+    float* ftop_n;        // new frontier (distinct buffers)
+    float* fsub_n;
+    const float* hb0;     // caller buffers u[0], u[1]: boundary shells by time level
+    const float* hb1;
+    const void* coef;
+    int64_t sk;
+    dims d;
+    host_weights wt;
+    int64_t t0, nt;
+    int first_centre, n_diamonds;
+    int dw;       // diamond width
+    int xo;       // output x extent per workgroup
+    int gx;       // x tiles
+    int zchunk;   // planes per z-chunk
+    int gz;       // z-chunks
+};
+
+bool blocked_supported(int kind, int dw);
+int blocked_default_dw(int kind);
+int blocked_max_xo(int kind, int dw);
+hipError_t launch_blocked_row(int kind, bool bf16, const blocked_row_args& a, hipStream_t s);
+
+}  // namespace stn

@@ -1,0 +1,300 @@
+// Temporally blocked scheme: diamond tiles along y, a wavefront streaming
+// along z inside each diamond (Sect. 4.1-4.3: the "CATS2"/1WD form of
+// wavefront diamond blocking; Sect. 5.1: several workers share one diamond).
+//
+// One launch processes one row of diamonds (the rows of Sect. 4.2 are
+// independent inside, dependent across: the launch boundary is the global
+// synchronisation between rows).  A workgroup owns one diamond, one x-tile and
+// one z-chunk and plays the role of the paper's thread group: its waves split
+// every time level of the frontline among themselves (Sect. 5.1) and meet at a
+// barrier after each level (Sect. 4.1, multi-thread wavefront).
+//
+// Inside a workgroup.  Level j (time t0 + j, j = 1 .. 2H-1) of the diamond is
+// produced at plane z_j = s - (j-1)R at stream step s: the frontline slope is
+// -1/R as in Sect. 4.1, since level j at plane z needs level j-1 at planes
+// z-R .. z+R and level j-1 has just produced plane z+R.  Every level keeps the
+// last 2R+1 planes of its values in registers (a z-queue per column); the
+// centre plane of the level below is staged in LDS for the in-plane
+// neighbours.  So all intermediate levels stay on chip and HBM sees, per
+// diamond, the lower edge it reads and the upper edge it writes.
+//
+// Frontier storage.  Between rows the state is the "frontier": for every
+// point the two newest levels computed so far (top and the one below).  Row r
+// reads the old frontier and writes a new one into a separate pair of
+// buffers, so that workgroups that overlap in x or z (they recompute a halo of
+// R per remaining level, redundant work instead of communication) never read
+// what another workgroup of the same launch writes.  The two pairs alternate
+// between rows; one pair is the caller's two time-level buffers.
+//
+// Boundary values (the shell of width halo) are always read from the caller's
+// buffer that holds that time level in the two-buffer convention.
+#include <algorithm>
+
+#include "blocked.h"
+#include "common.h"
+#include "point_ops.h"
+
+namespace stn {
+
+namespace {
+
+template <int KIND, typename CT, int H, int NWV, int XCH>
+__global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
+    const float* ftop_o, const float* fsub_o, float* ftop_n, float* fsub_n,
+    const float* __restrict__ hb0, const float* __restrict__ hb1, const CT* __restrict__ coef,
+    int64_t sk, int nx, int ny, int nz, int64_t sy, int64_t sz, int64_t org, weights wt, int t0,
+    int nt, int first_centre, int XO, int gx, int zchunk, int gz, int ntiles) {
+    constexpr int R = kind_traits<KIND>::R;
+    constexpr int K = kind_traits<KIND>::K;
+    constexpr bool LF = kind_traits<KIND>::leapfrog;
+    constexpr int L = 2 * H - 1;
+    constexpr int Q = 2 * R + 1;
+    constexpr int DW = 2 * R * H;
+    constexpr int YT = DW + 2 * R;
+    constexpr int XT = 64 * XCH;
+    constexpr int NCOL = YT * XCH;
+    constexpr int CPT = (NCOL + NWV - 1) / NWV;
+    __shared__ float lds[2][YT * XT];
+
+    const int tile = xcd_remap(blockIdx.x, ntiles);
+    const int g = tile % gx;
+    const int zc = (tile / gx) % gz;
+    const int di = tile / (gx * gz);
+    const int yc = first_centre + di * DW;
+    const int x0 = g * XO;
+    const int z0 = zc * zchunk;
+    const int z1 = min(nz, z0 + zchunk);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+
+    // All addressing is relative to the tile corner (x0 - RL, y_c - RH - R, 0),
+    // so a column offset fits in 32 bits.
+    const int ybase = yc - R * H - R;
+    const int xbase = x0 - R * L;
+    const int64_t cb = org + (int64_t)ybase * sy + xbase;
+    const float* FT = ftop_o + cb;
+    const float* FS = fsub_o + cb;
+    float* NT_ = ftop_n + cb;
+    float* NS = fsub_n + cb;
+    const float* B0 = hb0 + cb;
+    const float* B1 = hb1 + cb;
+    const CT* W = coef ? coef + cb : nullptr;
+
+    // ---- per-column geometry, packed (fixed for the whole stream) -----------
+    // off: yl*sy + xl.  info bits: [0,8) jold+64, [8,16) jnew+64, [16,24)
+    // jxmax+64, 24 needed (exists, within R of the interior), 25 interior in
+    // x and y, 26 new frontier written here.  jold/jnew are the levels (t - t0)
+    // of the old and new frontier tops; jxmax the last level whose x-range
+    // [x0 - R(L-j), x0 + XO + R(L-j)) contains the column.
+    int off[CPT];
+    uint32_t info[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int q = wv + NWV * c;
+        const int yl = q / XCH;
+        const int xl = (q % XCH) * 64 + lane;
+        const int y = ybase + yl;
+        const int x = xbase + xl;
+        off[c] = yl * (int)sy + xl;
+        const bool col = q < NCOL;
+        const bool yneed = y >= -R && y < ny + R;
+        const bool xneed = x >= -R && x < nx + R;
+        const bool inr = x >= 0 && x < nx && y >= 0 && y < ny;
+        const int xr = max(max(x0 - x, x - (x0 + XO - 1)), 0);
+        const int jx = max(L - (xr + R - 1) / R, -1);
+        const int d = y - yc;
+        int k = d >= 0 ? d / R : (-d - 1) / R;
+        const bool own = k <= H - 1;
+        if (!own) k = 2 * H - 1 - k;  // flank rows belong to a neighbour of this row
+        const int to = min(max(t0 + k, 0), nt);
+        const int tn = own ? max(to, min(t0 + 2 * H - 1 - k, nt)) : to;
+        const bool outc = col && own && inr && x >= x0 && x < x0 + XO;
+        info[c] = (uint32_t)(to - t0 + 64) | ((uint32_t)(tn - t0 + 64) << 8) |
+                  ((uint32_t)(jx + 64) << 16) | ((col && yneed && xneed) ? (1u << 24) : 0u) |
+                  (inr ? (1u << 25) : 0u) | (outc ? (1u << 26) : 0u);
+    }
+
+    auto lds_index = [&](int c) {
+        const int q = wv + NWV * c;
+        return (q / XCH) * XT + (q % XCH) * 64 + lane;
+    };
+
+    // ---- register z-queues: q[j][c][i] = level j at plane z_j - 2R + i ------
+    float qv[L][CPT][Q];
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) qv[j][c][i] = 0.0f;
+
+    int lb = 0;  // LDS buffer toggle (uniform)
+    const int s_begin = z0 - R * (L + 1);
+    const int s_end = z1 + R * (L - 1);
+    for (int s = s_begin; s < s_end; ++s) {
+        // Recompute the per-column masks every step instead of keeping
+        // (levels x columns) loop-invariant masks alive in scalar registers.
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) asm volatile("" : "+v"(info[c]));
+#pragma unroll
+        for (int j = 0; j <= L; ++j) {
+            const int t = t0 + j;
+            const int z = s - (j - 1) * R;
+            // plane range of level j: [z0 - R(L-j), z1 + R(L-j)) within [-R, nz + R)
+            const bool zact = z >= max(z0 - R * (L - j), -R) && z < min(z1 + R * (L - j), nz + R) &&
+                              t >= -1 && t <= nt;
+            const bool zin = z >= 0 && z < nz;
+            const bool zout = z >= z0 && z < z1;
+            const int64_t zo = (int64_t)z * sz;
+            const float* HB = LF ? (((t + 1) & 1) ? B1 : B0) : ((t & 1) ? B1 : B0);
+            bool cmp[CPT];
+            float val[CPT];
+            // 1. loads: frontier and boundary values of level j at plane z
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                cmp[c] = false;
+                val[c] = 0.0f;
+                const int jold = (int)(info[c] & 255u) - 64;
+                const int jnew = (int)((info[c] >> 8) & 255u) - 64;
+                const int jxm = (int)((info[c] >> 16) & 255u) - 64;
+                if (zact && (info[c] & (1u << 24)) && j <= jxm) {
+                    if (!((info[c] & (1u << 25)) && zin)) {
+                        val[c] = HB[zo + off[c]];
+                    } else if (j == jold) {
+                        val[c] = FT[zo + off[c]];
+                    } else if (j == jold - 1) {
+                        val[c] = FS[zo + off[c]];
+                    } else if (j > jold && j <= jnew) {
+                        cmp[c] = true;
+                    }
+                }
+            }
+            if (j >= 1) {
+                // 2. stage the centre plane (z) of level j-1 for in-plane neighbours
+                const int jp = j >= 1 ? j - 1 : 0;
+                float* P = lds[lb];
+#pragma unroll
+                for (int c = 0; c < CPT; ++c)
+                    if (wv + NWV * c < NCOL) P[lds_index(c)] = qv[jp][c][R];
+                __syncthreads();
+                // 3. compute
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    if (cmp[c]) {
+                        float Wv[kslots<KIND>];
+                        Wv[0] = 0.0f;
+                        if constexpr (K > 0) {
+#pragma unroll
+                            for (int kk = 0; kk < K; ++kk)
+                                Wv[kk] = load_coef(W, kk * sk + zo + off[c]);
+                        }
+                        float pv = 0.0f;
+                        if constexpr (LF) {
+                            if (j == 1)
+                                pv = FS[zo + off[c]];
+                            else
+                                pv = qv[j >= 2 ? j - 2 : 0][c][0];
+                        }
+                        const int li = lds_index(c);
+                        nbhd<R> n;
+                        n.c = qv[jp][c][R];
+#pragma unroll
+                        for (int r = 1; r <= R; ++r) {
+                            n.pair[0][r - 1] = P[li - r] + P[li + r];
+                            n.pair[1][r - 1] = P[li - r * XT] + P[li + r * XT];
+                            n.pair[2][r - 1] = qv[jp][c][R - r] + qv[jp][c][R + r];
+                        }
+                        n.m1[0] = P[li - 1];
+                        n.p1[0] = P[li + 1];
+                        n.m1[1] = P[li - XT];
+                        n.p1[1] = P[li + XT];
+                        n.m1[2] = qv[jp][c][R - 1];
+                        n.p1[2] = qv[jp][c][R + 1];
+                        val[c] = update<KIND>(wt, Wv, n, pv);
+                    }
+                    // keep one column's temporaries live at a time
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                lb ^= 1;
+            }
+            // 4. push into the queue of level j and write the new frontier
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                if (j < L) {
+#pragma unroll
+                    for (int i = 0; i < Q - 1; ++i) qv[j < L ? j : 0][c][i] = qv[j < L ? j : 0][c][i + 1];
+                    qv[j < L ? j : 0][c][Q - 1] = val[c];
+                }
+                if (zact && zout && (info[c] & (1u << 26))) {
+                    const int jnew = (int)((info[c] >> 8) & 255u) - 64;
+                    if (j == jnew)
+                        NT_[zo + off[c]] = val[c];
+                    else if (j == jnew - 1)
+                        NS[zo + off[c]] = val[c];
+                }
+            }
+        }
+    }
+}
+
+// Register and LDS budget per (R, H): workgroup shape and columns per lane.
+template <int KIND, typename CT, int H, int NWV, int XCH>
+hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
+    constexpr int R = kind_traits<KIND>::R;
+    const int ntiles = a.n_diamonds * a.gx * a.gz;
+    if (ntiles <= 0) return hipSuccess;
+    weights wt;
+    for (int i = 0; i < 5; ++i) wt.w[i] = a.wt.w[i];
+    wt.alpha = a.wt.alpha;
+    (void)R;
+    hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH>), dim3(ntiles), dim3(NWV * 64), 0,
+                       s, a.ftop_o, a.fsub_o, a.ftop_n, a.fsub_n, a.hb0, a.hb1,
+                       static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.sy,
+                       a.d.sz, a.d.org(), wt, (int)a.t0, (int)a.nt, a.first_centre, a.xo, a.gx,
+                       a.zchunk, a.gz, ntiles);
+    return hipGetLastError();
+}
+
+template <int KIND, typename CT>
+hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
+    constexpr int R = kind_traits<KIND>::R;
+    const int H = a.dw / (2 * R);
+    if constexpr (R == 1) {
+        if (H == 4) return launch_cfg<KIND, CT, 4, 10, 2>(a, s);
+        if (H == 2) return launch_cfg<KIND, CT, 2, 6, 2>(a, s);
+        if (H == 6) return launch_cfg<KIND, CT, 6, 14, 2>(a, s);
+    } else {
+        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 2>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool blocked_supported(int kind, int dw) {
+    const int R = (kind == 1 || kind == 2) ? 1 : 4;
+    if (dw % (2 * R) != 0) return false;
+    const int H = dw / (2 * R);
+    return R == 1 ? (H == 2 || H == 4 || H == 6) : (H == 2);
+}
+
+int blocked_default_dw(int kind) { return (kind == 1 || kind == 2) ? 8 : 16; }
+
+int blocked_max_xo(int kind, int dw) {
+    const int R = (kind == 1 || kind == 2) ? 1 : 4;
+    const int L = dw / R - 1;
+    return 128 - 2 * R * L;
+}
+
+hipError_t launch_blocked_row(int kind, bool bf16, const blocked_row_args& a, hipStream_t s) {
+    switch (kind) {
+    case 1: return launch_kind<1, float>(a, s);
+    case 2: return bf16 ? launch_kind<2, uint16_t>(a, s) : launch_kind<2, float>(a, s);
+    case 3: return bf16 ? launch_kind<3, uint16_t>(a, s) : launch_kind<3, float>(a, s);
+    case 4: return launch_kind<4, float>(a, s);
+    case 5: return bf16 ? launch_kind<5, uint16_t>(a, s) : launch_kind<5, float>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace stn

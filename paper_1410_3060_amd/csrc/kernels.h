@@ -1,0 +1,32 @@
+// Host-side launchers of the HIP kernels (internal to libstencil.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stn {
+
+// Geometry of one call: interior sizes, boundary width, element strides.
+struct dims {
+    int nx, ny, nz, h;
+    int64_t sy, sz;
+    // element offset of interior (0,0,0) from the padded origin
+    int64_t org() const { return (int64_t)h * sz + (int64_t)h * sy + h; }
+};
+
+struct host_weights {
+    float w[5];
+    float alpha;
+};
+
+// One naive time step (Sect. 4.1).  Jacobi kinds: out <- A(cur).  Leapfrog
+// kinds: out <- 2 cur - prev + alpha L8(cur); out may equal prev.  Pointers
+// address padded origins.  coef_bf16 selects uint16 BF16 coefficient storage.
+hipError_t launch_naive_step(int kind, bool coef_bf16, const float* cur, const float* prev,
+                             float* out, const void* coef, int64_t sk, const dims& d,
+                             const host_weights& wt, int zchunk, hipStream_t s);
+
+// Planes per z-chunk the naive launcher picks when zchunk == 0.
+int naive_default_zchunk(int kind, const dims& d);
+
+}  // namespace stn

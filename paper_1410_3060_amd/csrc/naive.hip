@@ -1,0 +1,234 @@
+// Naive scheme (Sect. 4.1): one full sweep of the lattice per time step.
+//
+// GPU mapping.  A workgroup of 4 waves owns a 64 x TY tile of (x, y) columns
+// and streams along z through a chunk of planes (the 2.5D form of the
+// spatial blocking of Sect. 3.3: every value of the input level is read from
+// HBM once per sweep).  Each lane keeps, for each of its RPT columns, the
+// 2R+1 values u(z-R..z+R) in registers; the current plane with its x/y halo
+// of width R is staged in LDS (double buffered, one barrier per plane) for the
+// in-plane neighbours.  x is the lane index, so every global access of a wave
+// is one contiguous 256-byte row.  Coefficients are read once per point.
+#include "common.h"
+#include "kernels.h"
+#include "point_ops.h"
+
+namespace stn {
+
+namespace {
+
+constexpr int NT = 256;  // threads per workgroup
+constexpr int NW = NT / 64;
+
+template <int KIND, typename CT, int RPT>
+__global__ __launch_bounds__(NT) void naive_step_kernel(
+    const float* __restrict__ cur, const float* prev, float* out, const CT* __restrict__ coef,
+    int64_t sk, int nx, int ny, int nz, int64_t sy, int64_t sz, int64_t org, weights wt,
+    int zchunk, int gx, int gy, int ntiles) {
+    constexpr int R = kind_traits<KIND>::R;
+    constexpr int K = kind_traits<KIND>::K;
+    constexpr int Q = 2 * R + 1;
+    constexpr int TY = NW * RPT;
+    constexpr int LW = 64 + 2 * R;
+    constexpr int LH = TY + 2 * R;
+    __shared__ float lds[2][LH][LW];
+
+    const int tile = xcd_remap(blockIdx.x, ntiles);
+    const int bx = tile % gx;
+    const int by = (tile / gx) % gy;
+    const int bz = tile / (gx * gy);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int x0 = bx * 64, y0 = by * TY;
+    const int z0 = bz * zchunk;
+    const int z1 = min(nz, z0 + zchunk);
+    const int x = x0 + lane;
+
+    // interior-origin based pointers: element (x, y, z) at p + z*sz + y*sy + x
+    const float* C = cur + org;
+    const float* P = prev ? prev + org : nullptr;
+    float* O = out + org;
+    const CT* W = coef ? coef + org : nullptr;
+
+    // columns of this lane: y = y0 + wv + NW*i
+    int64_t colo[RPT];
+    bool ld_ok[RPT], st_ok[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int y = y0 + wv + NW * i;
+        colo[i] = (int64_t)y * sy + x;
+        ld_ok[i] = (x < nx + R) && (y < ny + R);
+        st_ok[i] = (x < nx) && (y < ny);
+    }
+
+    // y-halo rows handled by this wave: hr = wv + NW*j over [0, 2R)
+    constexpr int HYJ = (2 * R + NW - 1) / NW;
+    int64_t hyo[HYJ];
+    bool hy_ok[HYJ];
+    int hy_row[HYJ];
+#pragma unroll
+    for (int j = 0; j < HYJ; ++j) {
+        const int hr = wv + NW * j;
+        const int ly = hr < R ? hr - R : TY + (hr - R);  // local row in [-R,0) or [TY,TY+R)
+        const int y = y0 + ly;
+        hy_row[j] = ly + R;
+        hyo[j] = (int64_t)y * sy + x;
+        hy_ok[j] = (hr < 2 * R) && (x < nx + R) && (y < ny + R);
+    }
+    // x-halo columns: thread id < 2R*TY loads one value per plane
+    const int hxi = threadIdx.x;
+    const bool hx_any = hxi < 2 * R * TY;
+    int hx_lx = 0, hx_ly = 0;
+    int64_t hxo = 0;
+    bool hx_ok = false;
+    if (hx_any) {
+        const int col = hxi % (2 * R), row = hxi / (2 * R);
+        const int gxp = col < R ? x0 - R + col : x0 + 64 + (col - R);
+        const int y = y0 + row;
+        hx_lx = (col < R ? col : 64 + R + (col - R));
+        hx_ly = row + R;
+        hxo = (int64_t)y * sy + gxp;
+        hx_ok = (gxp < nx + R) && (y < ny + R);
+    }
+
+    // register queues: q[i][k] = u(column i, plane z - R + k)
+    float q[RPT][Q];
+    float nxt[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+#pragma unroll
+        for (int k = 1; k < Q; ++k)
+            q[i][k] = ld_ok[i] ? C[(int64_t)(z0 - R - 1 + k) * sz + colo[i]] : 0.0f;
+        nxt[i] = ld_ok[i] ? C[(int64_t)(z0 + R) * sz + colo[i]] : 0.0f;
+    }
+    float hy[HYJ], hx = 0.0f;
+#pragma unroll
+    for (int j = 0; j < HYJ; ++j) hy[j] = hy_ok[j] ? C[(int64_t)z0 * sz + hyo[j]] : 0.0f;
+    if (hx_ok) hx = C[(int64_t)z0 * sz + hxo];
+
+    for (int z = z0; z < z1; ++z) {
+        const int b = (z - z0) & 1;
+        const int64_t zo = (int64_t)z * sz;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+#pragma unroll
+            for (int k = 0; k < Q - 1; ++k) q[i][k] = q[i][k + 1];
+            q[i][Q - 1] = nxt[i];
+            lds[b][R + wv + NW * i][R + lane] = q[i][R];
+        }
+#pragma unroll
+        for (int j = 0; j < HYJ; ++j)
+            if (wv + NW * j < 2 * R) lds[b][hy_row[j]][R + lane] = hy[j];
+        if (hx_any) lds[b][hx_ly][hx_lx] = hx;
+
+        // prefetch the next plane while this one is computed
+        if (z + 1 < z1) {
+            const int64_t zn = (int64_t)(z + 1 + R) * sz, z1o = (int64_t)(z + 1) * sz;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (ld_ok[i]) nxt[i] = C[zn + colo[i]];
+#pragma unroll
+            for (int j = 0; j < HYJ; ++j)
+                if (hy_ok[j]) hy[j] = C[z1o + hyo[j]];
+            if (hx_ok) hx = C[z1o + hxo];
+        }
+        // coefficients and the older level for this plane
+        float Wv[RPT][kslots<KIND>];
+        float pv[RPT];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            pv[i] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < kslots<KIND>; ++k) Wv[i][k] = 0.0f;
+            if (st_ok[i]) {
+                if constexpr (K > 0) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) Wv[i][k] = load_coef(W, k * sk + zo + colo[i]);
+                }
+                if constexpr (kind_traits<KIND>::leapfrog) pv[i] = P[zo + colo[i]];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int ly = R + wv + NW * i, lx = R + lane;
+            nbhd<R> n;
+            n.c = q[i][R];
+#pragma unroll
+            for (int r = 1; r <= R; ++r) {
+                n.pair[0][r - 1] = lds[b][ly][lx - r] + lds[b][ly][lx + r];
+                n.pair[1][r - 1] = lds[b][ly - r][lx] + lds[b][ly + r][lx];
+                n.pair[2][r - 1] = q[i][R - r] + q[i][R + r];
+            }
+            n.m1[0] = lds[b][ly][lx - 1];
+            n.p1[0] = lds[b][ly][lx + 1];
+            n.m1[1] = lds[b][ly - 1][lx];
+            n.p1[1] = lds[b][ly + 1][lx];
+            n.m1[2] = q[i][R - 1];
+            n.p1[2] = q[i][R + 1];
+            const float v = update<KIND>(wt, Wv[i], n, pv[i]);
+            if (st_ok[i]) O[zo + colo[i]] = v;
+        }
+    }
+}
+
+template <int KIND>
+constexpr int naive_rpt() {
+    return kind_traits<KIND>::R == 1 ? 8 : 4;
+}
+
+template <int KIND, typename CT>
+hipError_t launch_kind(const float* cur, const float* prev, float* out, const void* coef,
+                       int64_t sk, const dims& d, const host_weights& hw, int zchunk,
+                       hipStream_t s) {
+    constexpr int RPT = naive_rpt<KIND>();
+    constexpr int TY = NW * RPT;
+    const int gx = (d.nx + 63) / 64, gy = (d.ny + TY - 1) / TY;
+    const int gz = (d.nz + zchunk - 1) / zchunk;
+    const long long ntiles = (long long)gx * gy * gz;
+    if (ntiles <= 0) return hipSuccess;
+    if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    weights wt;
+    for (int i = 0; i < 5; ++i) wt.w[i] = hw.w[i];
+    wt.alpha = hw.alpha;
+    hipLaunchKernelGGL((naive_step_kernel<KIND, CT, RPT>), dim3((unsigned)ntiles), dim3(NT), 0, s,
+                       cur, prev, out, static_cast<const CT*>(coef), sk, d.nx, d.ny, d.nz, d.sy,
+                       d.sz, d.org(), wt, zchunk, gx, gy, (int)ntiles);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int naive_default_zchunk(int kind, const dims& d) {
+    const int R = (kind == 1 || kind == 2) ? 1 : 4;
+    const int TY = NW * (R == 1 ? 8 : 4);
+    const long long txy = (long long)((d.nx + 63) / 64) * ((d.ny + TY - 1) / TY);
+    // aim at >= 2048 workgroups (8 per CU) with chunks of at least 16R planes
+    long long nzc = (2048 + txy - 1) / (txy > 0 ? txy : 1);
+    if (nzc < 1) nzc = 1;
+    int zc = (int)((d.nz + nzc - 1) / nzc);
+    if (zc < 16 * R) zc = 16 * R;
+    if (zc > d.nz) zc = d.nz > 0 ? d.nz : 1;
+    return zc;
+}
+
+hipError_t launch_naive_step(int kind, bool bf16, const float* cur, const float* prev, float* out,
+                             const void* coef, int64_t sk, const dims& d, const host_weights& wt,
+                             int zchunk, hipStream_t s) {
+    if (zchunk <= 0) zchunk = naive_default_zchunk(kind, d);
+    switch (kind) {
+    case 1: return launch_kind<1, float>(cur, prev, out, coef, sk, d, wt, zchunk, s);
+    case 2:
+        return bf16 ? launch_kind<2, uint16_t>(cur, prev, out, coef, sk, d, wt, zchunk, s)
+                    : launch_kind<2, float>(cur, prev, out, coef, sk, d, wt, zchunk, s);
+    case 3:
+        return bf16 ? launch_kind<3, uint16_t>(cur, prev, out, coef, sk, d, wt, zchunk, s)
+                    : launch_kind<3, float>(cur, prev, out, coef, sk, d, wt, zchunk, s);
+    case 4: return launch_kind<4, float>(cur, prev, out, coef, sk, d, wt, zchunk, s);
+    case 5:
+        return bf16 ? launch_kind<5, uint16_t>(cur, prev, out, coef, sk, d, wt, zchunk, s)
+                    : launch_kind<5, float>(cur, prev, out, coef, sk, d, wt, zchunk, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace stn

@@ -1,0 +1,159 @@
+"""Host-side checks of libstencil.so that need no GPU: the library loads,
+exports every entry point include/stencil.h declares, and rejects every bad
+argument before any HIP call (so the error paths run on a CPU-only host)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1410_3060_amd as st
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # never dereferenced: validation happens before any device call
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "stencil.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(stencil_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = st.load()
+    names = header_functions()
+    assert set(names) == set(st.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layouts_match_header():
+    # sizes of the C structs as laid out by the x86-64 SysV ABI
+    assert ctypes.sizeof(st._Grid) == 48
+    assert ctypes.sizeof(st._Coeffs) == 4 + 4 + 8 + 8 + 40 + 8
+    assert ctypes.sizeof(st._Tuning) == 24
+
+
+def make_ctx(scheme=st.NAIVE, **kw):
+    lib = st.load()
+    t = st._Tuning(kw.get("dw", 0), 0, kw.get("zchunk", 0), kw.get("ckpt", 0), kw.get("limit", 0))
+    h = ctypes.c_void_p()
+    rc = lib.stencil_create(ctypes.byref(h), scheme, ctypes.byref(t), None)
+    return rc, h
+
+
+def grid(nx=16, ny=16, nz=16, halo=4, sy=None, sz=None, u0=FAKE, u1=FAKE + 4096):
+    g = st._Grid()
+    g.nx, g.ny, g.nz, g.halo = nx, ny, nz, halo
+    g.sy = sy if sy is not None else nx + 2 * halo
+    g.sz = sz if sz is not None else g.sy * (ny + 2 * halo)
+    g.u[0], g.u[1] = u0, u1
+    return g
+
+
+def coeffs(kind, g, dtype=st.F32, arrays=FAKE * 7, sk=None):
+    c = st._Coeffs()
+    c.dtype = dtype
+    c.arrays = arrays if st.NCOEF[kind] else None
+    c.sk = sk if sk is not None else g.sz * (g.nz + 2 * g.halo)
+    for i, v in enumerate(st.L8_WEIGHTS):
+        c.w[i] = v
+    c.alpha = 0.1
+    return c
+
+
+def run(h, kind, g, c, nt=3):
+    slot = ctypes.c_int(-7)
+    rc = st.load().stencil_run(h, kind, ctypes.byref(g) if g else None,
+                               ctypes.byref(c) if c else None, nt, ctypes.byref(slot))
+    return rc, slot.value
+
+
+def msg():
+    return st.load().stencil_last_error().decode()
+
+
+def test_create_validates_tuning():
+    rc, h = make_ctx(scheme=7)
+    assert rc == 1 and "scheme" in msg()
+    rc, h = make_ctx(dw=5)
+    assert rc == 1 and "dw" in msg()
+    rc, h = make_ctx(zchunk=-1)
+    assert rc == 1
+    rc, h = make_ctx()
+    assert rc == 0 and h.value
+    st.load().stencil_destroy(h)
+    assert st.load().stencil_create(None, 0, None, None) == 1
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3, 4, 5])
+def test_run_argument_errors(kind):
+    rc, h = make_ctx()
+    assert rc == 0
+    R = st.RADIUS[kind]
+    try:
+        g = grid(halo=R)
+        c = coeffs(kind, g)
+        assert run(None, kind, g, c)[0] == 1
+        assert run(h, 0, g, c)[0] == 1
+        assert run(h, 6, g, c)[0] == 1
+        assert run(h, kind, None, c)[0] == 1
+        assert run(h, kind, g, None)[0] == 1
+        assert run(h, kind, g, c, nt=-1)[0] == 1 and "nt" in msg()
+        assert run(h, kind, grid(halo=R - 1), c)[0] == 1 and "halo" in msg()
+        assert run(h, kind, grid(halo=R, nx=-1), c)[0] == 1
+        assert run(h, kind, grid(halo=R, sy=16 + 2 * R - 1), c)[0] == 1 and "sy" in msg()
+        assert run(h, kind, grid(halo=R, sz=(16 + 2 * R) ** 2 - 1), c)[0] == 1 and "sz" in msg()
+        assert run(h, kind, grid(halo=R, u0=0), c)[0] == 1
+        assert run(h, kind, grid(halo=R, u1=FAKE), c)[0] == 1 and "distinct" in msg()
+        bad = coeffs(kind, g)
+        bad.dtype = 9
+        assert run(h, kind, g, bad)[0] == 1
+        bad = coeffs(kind, g)
+        bad.w[2] = float("nan")
+        assert run(h, kind, g, bad)[0] == 1
+        if st.NCOEF[kind]:
+            assert run(h, kind, g, coeffs(kind, g, arrays=0))[0] == 1
+            if st.NCOEF[kind] > 1:
+                assert run(h, kind, g, coeffs(kind, g, sk=g.sz))[0] == 1 and "sk" in msg()
+            # BF16 is accepted for variable kinds: nt = 0 returns before any device call
+            assert run(h, kind, g, coeffs(kind, g, dtype=st.BF16), nt=0)[0] == 0
+        else:
+            rc, _ = run(h, kind, g, coeffs(kind, g, dtype=st.BF16))
+            assert rc == 2 and "BF16" in msg()
+        # nt = 0 and empty grids are no-ops that report the slot of level nt
+        rc, slot = run(h, kind, g, c, nt=0)
+        assert rc == 0 and slot == (1 if kind in (4, 5) else 0)
+        rc, slot = run(h, kind, grid(halo=R, nx=0), c, nt=3)
+        assert rc == 0 and slot == (0 if kind in (4, 5) else 1)
+    finally:
+        st.load().stencil_destroy(h)
+
+
+def test_blocked_dw_must_fit_radius():
+    rc, h = make_ctx(scheme=st.BLOCKED, dw=6)
+    assert rc == 0
+    g = grid(halo=4)
+    assert run(h, 3, g, coeffs(3, g))[0] == 1 and "dw" in msg()
+    st.load().stencil_destroy(h)
+
+
+def test_adjoint_argument_errors():
+    lib = st.load()
+    rc, h = make_ctx()
+    g = grid(halo=4)
+    c = coeffs(5, g)
+    f = ctypes.c_void_p(FAKE)
+    assert lib.stencil_adjoint(h, 3, ctypes.byref(g), ctypes.byref(c), 5, f, f, f, f) == 2
+    assert lib.stencil_adjoint(h, 5, ctypes.byref(g), ctypes.byref(c), -1, f, f, f, f) == 1
+    assert lib.stencil_adjoint(h, 5, ctypes.byref(g), ctypes.byref(c), 5, None, f, f, f) == 1
+    assert lib.stencil_adjoint(None, 5, ctypes.byref(g), ctypes.byref(c), 5, f, f, f, f) == 1
+    lib.stencil_destroy(h)
+
+
+def test_sync_and_destroy_without_work():
+    rc, h = make_ctx()
+    assert st.load().stencil_sync(h) == 0
+    st.load().stencil_destroy(h)
+    st.load().stencil_destroy(None)
+    assert st.load().stencil_sync(None) == 1

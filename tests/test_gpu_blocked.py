@@ -1,0 +1,92 @@
+"""GPU parity of the temporally blocked scheme.
+
+The blocked scheme reorders the naive updates (diamond rows, wavefront along
+z) but evaluates every point with the same FMA order, so it must equal the
+naive scheme bit for bit -- on every interior point and without touching the
+boundary shell -- and both must match the FP64 oracle.  Cases cover both
+parities of the number of diamond rows, nt below, at and above the diamond
+half-height H, odd sizes with ragged x/y/z tiles, forced small z-chunks (so
+overlapping workgroups recompute halos) and BF16 coefficients."""
+import numpy as np
+import pytest
+
+import paper_1410_3060_amd as st
+import workloads
+
+from gpu_util import max_rel, rel_l2, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+SIZES = {1: (150, 45, 23), 2: (70, 37, 19), 3: (130, 41, 29), 4: (131, 39, 26), 5: (97, 35, 27)}
+# diamond widths per workload: R = 1 for workloads 1 and 3, R = 4 for 2, 4 and 5
+DWS = {1: [8, 4, 12], 2: [16], 3: [8, 4, 12], 4: [16], 5: [16]}
+
+
+def both(wl, dw, nt, **kw):
+    nb, nb_prev = run_gpu(wl, st.NAIVE, nt=nt)
+    bl, bl_prev = run_gpu(wl, st.BLOCKED, nt=nt, dw=dw, **kw)
+    return nb, nb_prev, bl, bl_prev
+
+
+def assert_bitwise(a, b, what):
+    if not np.array_equal(a, b):
+        d = np.argwhere(a != b)
+        raise AssertionError(f"{what}: {len(d)} points differ, first at (z,y,x)={tuple(d[0])}: "
+                             f"{a[tuple(d[0])]!r} vs {b[tuple(d[0])]!r}")
+
+
+@pytest.mark.parametrize("index", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("nt", [1, 2, 3, 4, 5, 9])
+def test_blocked_equals_naive_bitwise(index, nt):
+    wl = workloads.make(index, n=SIZES[index], nt=nt)
+    dw = DWS[index][0]
+    nb, nb_prev, bl, bl_prev = both(wl, dw, nt, zchunk=9)
+    assert_bitwise(bl, nb, f"workload {index} dw {dw} nt {nt}")
+    if nb_prev is not None:
+        assert_bitwise(bl_prev, nb_prev, f"workload {index} dw {dw} nt {nt} (level nt-1)")
+
+
+@pytest.mark.parametrize("index", [1, 3])
+@pytest.mark.parametrize("dw", [4, 12])
+def test_blocked_other_diamond_widths(index, dw):
+    for nt in (5, 6, 13):
+        wl = workloads.make(index, n=SIZES[index], nt=nt)
+        nb, _, bl, _ = both(wl, dw, nt)
+        assert_bitwise(bl, nb, f"workload {index} dw {dw} nt {nt}")
+
+
+@pytest.mark.parametrize("index", [1, 2, 3, 4, 5])
+def test_blocked_matches_oracle(index):
+    wl = workloads.make(index, n=SIZES[index], nt=10)
+    got, got_prev = run_gpu(wl, st.BLOCKED, dw=DWS[index][0])
+    want, want_prev = run_oracle(wl)
+    for g, w in ((got, want), (got_prev, want_prev)):
+        if g is None:
+            continue
+        e2, em = rel_l2(g, w, wl.halo), max_rel(g, w, wl.halo)
+        print(f"workload {index}: blocked rel-L2 {e2:.3e} max-rel {em:.3e}")
+        assert e2 <= TOL and em <= TOL
+
+
+@pytest.mark.parametrize("index", [3, 4, 5])
+def test_blocked_bf16_bitwise(index):
+    wl = workloads.make(index, n=SIZES[index], nt=7, coef_dtype="bf16")
+    nb, nb_prev, bl, bl_prev = both(wl, DWS[index][0], 7, zchunk=13)
+    assert_bitwise(bl, nb, f"workload {index} bf16")
+
+
+@pytest.mark.parametrize("index", [1, 4])
+def test_blocked_contiguous_layout(index):
+    wl = workloads.make(index, n=(77, 50, 33), nt=6)
+    nb, _ = run_gpu(wl, st.NAIVE, aligned=False)
+    bl, _ = run_gpu(wl, st.BLOCKED, aligned=False, dw=DWS[index][0])
+    assert_bitwise(bl, nb, f"workload {index} contiguous")
+
+
+def test_blocked_thin_and_tiny():
+    for n in [(1, 1, 1), (3, 70, 2), (64, 8, 1), (200, 3, 5)]:
+        wl = workloads.make(3, n=n, nt=5)
+        nb, _ = run_gpu(wl, st.NAIVE)
+        bl, _ = run_gpu(wl, st.BLOCKED, dw=8)
+        assert_bitwise(bl, nb, f"7pt var n={n}")
