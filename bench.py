@@ -208,7 +208,7 @@ def adjoint_leg(st, workloads, torch, np, stream, args):
     out = {}
     for scheme, name in ((st.NAIVE, "naive"), (st.BLOCKED, "blocked")):
         ctx = st.Context(scheme, ckpt_every=k, stream=stream)
-        a, b = up.clone(), u0.clone()
+        a, b = st.field_like(up, h), st.field_like(u0, h)
         ts_f, ts_a = [], []
         for i in range(1 + max(1, args.steps // 2)):
             a.copy_(up)

@@ -234,6 +234,15 @@ def plan_rows(kind: int, dw: int, ny: int, nt: int):
     return [tuple(buf[4 * i: 4 * i + 4]) for i in range(n)]
 
 
+def field_like(t, halo: int):
+    """A new aligned field (see alloc_field) holding a copy of the 3D field t."""
+    pz, py, px = t.shape
+    out = alloc_field((px - 2 * halo, py - 2 * halo, pz - 2 * halo), halo, dtype=t.dtype,
+                      device=t.device)
+    out.copy_(t)
+    return out
+
+
 def alloc_field(n3, halo: int, *, count: Optional[int] = None, dtype=None, device="cuda"):
     """Zeroed padded field(s) laid out for coalesced access.
 

@@ -1,0 +1,84 @@
+"""torch.autograd binding of the leapfrog with a domain-sized coefficient.
+
+``wave_varc(u_prev, u0, c, nt)`` returns u_nt of
+    u_{n+1} = 2 u_n - u_{n-1} + c * L8(u_n)        (Fig. 1e, alpha = c(x))
+computed by libstencil.so; its backward runs the library's adjoint (reverse
+time stepping from checkpoints recorded during the forward, every
+``ckpt_every`` steps, with recomputation in between) and returns the
+gradients with respect to u_prev, u0 and c.  Only the marshalling lives here.
+
+The boundary shell of the fields is a fixed Dirichlet boundary: gradients
+with respect to shell entries are reported as zero.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import (BLOCKED, KIND_25PT_WAVE_VARC, L8_WEIGHTS, NAIVE, Context, alloc_field)
+
+
+def _aligned_copy(t, halo):
+    pz, py, px = t.shape[-3:]
+    out = alloc_field((px - 2 * halo, py - 2 * halo, pz - 2 * halo), halo)
+    out.copy_(t.reshape(pz, py, px))
+    return out
+
+
+class WaveFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u_prev, u0, c, nt: int, halo: int, ckpt_every: int, scheme: int):
+        if not (u_prev.is_cuda and u0.is_cuda and c.is_cuda):
+            raise ValueError("wave_varc needs CUDA tensors")
+        k = ckpt_every if ckpt_every > 0 else max(1, int(round(math.sqrt(max(nt, 1)))))
+        a = _aligned_copy(u_prev.detach().float(), halo)
+        b = _aligned_copy(u0.detach().float(), halo)
+        cc = _aligned_copy(c.detach().float(), halo)
+        c4 = cc.unsqueeze(0)
+        sctx = Context(scheme, ckpt_every=k)
+        slot = sctx.run(KIND_25PT_WAVE_VARC, a, b, nt, halo=halo, coef=c4, w=L8_WEIGHTS)
+        out = (a, b)[slot]
+        # the initial state, for a backward without a usable recording
+        ctx.sctx = sctx
+        ctx.nt, ctx.halo = nt, halo
+        ctx.c4 = c4
+        ctx.init = (_aligned_copy(u_prev.detach().float(), halo),
+                    _aligned_copy(u0.detach().float(), halo))
+        ctx.shape = u0.shape
+        ctx.c_dtype = c.dtype
+        ctx.c_shape = c.shape
+        return out.clone().reshape(u0.shape)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        halo = ctx.halo
+        seed = _aligned_copy(grad_out.detach().float(), halo)
+        # the boundary shell is not a state variable: its seed is dropped
+        shell = torch.ones_like(seed, dtype=torch.bool)
+        shell[halo:seed.shape[0] - halo, halo:seed.shape[1] - halo, halo:seed.shape[2] - halo] = False
+        seed.masked_fill_(shell, 0.0)
+        n3 = (seed.shape[2] - 2 * halo, seed.shape[1] - 2 * halo, seed.shape[0] - 2 * halo)
+        g0 = alloc_field(n3, halo)
+        gm1 = alloc_field(n3, halo)
+        gc = alloc_field(n3, halo, dtype=torch.float64)
+        up, u0 = ctx.init
+        ctx.sctx.adjoint(up, u0, ctx.nt, halo=halo, coef=ctx.c4, w=L8_WEIGHTS, seed=seed,
+                         grad_u0=g0, grad_um1=gm1, grad_c=gc)
+        ctx.sctx.close()
+        gc_out = gc.to(ctx.c_dtype).reshape(ctx.c_shape)
+        return (gm1.clone().reshape(ctx.shape), g0.clone().reshape(ctx.shape), gc_out, None, None,
+                None, None)
+
+
+def wave_varc(u_prev, u0, c, nt: int, *, halo: int = 4, ckpt_every: int = 0,
+              scheme: int = NAIVE):
+    """u_nt of the leapfrog with c(x); differentiable in u_prev, u0 and c.
+
+    Fields are (nz+2h, ny+2h, nx+2h) CUDA tensors (padded, x fastest).  Pass
+    the same tensor as u_prev and u0 for a start from rest; autograd then adds
+    the two gradients.  ``scheme`` is NAIVE or BLOCKED for the forward.
+    """
+    if scheme not in (NAIVE, BLOCKED):
+        raise ValueError("scheme must be NAIVE or BLOCKED")
+    return WaveFunction.apply(u_prev, u0, c, int(nt), int(halo), int(ckpt_every), int(scheme))
