@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--n", type=int, default=None, help="override the grid size (testing only)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the device-to-device copy probe and print its bandwidth")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -79,6 +81,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    probe = copy_probe(torch)
+    if args.copy_probe:
+        print(json.dumps({"copy_probe": probe}), flush=True)
+        return
 
     t_gen = time.time()
     wl = workloads.make(4, n=args.n)
@@ -131,6 +137,7 @@ def main():
     achieved = bpl_b * lups / n_rows / avg_launch / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "copy_probe_GBps": probe["GBps"],
                 "kernel": "blocked_row_kernel<3,float,H=%d>" % H,
                 "bytes_per_lup": round(bpl_b, 3), "avg_launch_ms": round(avg_launch * 1e3, 4)}
 
@@ -189,6 +196,28 @@ def main():
         "extras": extras,
     }
     print(json.dumps(line), flush=True)
+
+
+def copy_probe(torch, nbytes=1 << 32, reps=10):
+    """Attainable HBM bandwidth: a plain device-to-device copy of 4 GiB (the
+    analogue of the STREAM COPY figure b_S the paper's roofline uses).
+    Counts read + write bytes.  Also the known-size kernel that calibrates
+    rocprof's FETCH_SIZE / WRITE_SIZE counters."""
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return {"bytes_per_copy": 2 * nbytes, "GBps": round(2 * nbytes / sec / 1e9, 1),
+            "ms": round(sec * 1e3, 3)}
 
 
 def adjoint_leg(st, workloads, torch, np, stream, args):

@@ -38,7 +38,7 @@ namespace stn {
 
 namespace {
 
-template <int KIND, typename CT, int H, int NWV, int XCH>
+template <int KIND, typename CT, int H, int NWV, int XCH, bool G0>
 __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const float* ftop_o, const float* fsub_o, float* ftop_n, float* fsub_n,
     const float* __restrict__ hb0, const float* __restrict__ hb1, const CT* __restrict__ coef,
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     constexpr int XT = 64 * XCH;
     constexpr int NCOL = YT * XCH;
     constexpr int CPT = (NCOL + NWV - 1) / NWV;
-    __shared__ float lds[2][YT * XT];
+    __shared__ float lds[2][L][YT * XT];
 
     const int tile = xcd_remap(blockIdx.x, ntiles);
     const int g = tile % gx;
@@ -118,8 +118,45 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         const int q = wv + NWV * c;
         return (q / XCH) * XT + (q % XCH) * 64 + lane;
     };
+    // What level j holds at column c and plane z: 0 not needed here, 1
+    // boundary value, 2 old frontier top, 3 old frontier level below it,
+    // 4 computed by this workgroup.
+    auto classify = [&](int c, int j, bool zact, bool zin) -> int {
+        const uint32_t f = info[c];
+        const int jold = (int)(f & 255u) - 64;
+        const int jnew = (int)((f >> 8) & 255u) - 64;
+        const int jxm = (int)((f >> 16) & 255u) - 64;
+        if (!(zact && (f & (1u << 24)) && j <= jxm)) return 0;
+        if (!((f & (1u << 25)) && zin)) return 1;
+        if (j == jold) return 2;
+        if (j == jold - 1) return 3;
+        if (j > jold && j <= jnew) return 4;
+        return 0;
+    };
+    auto level_active = [&](int j, int z) {
+        const int t = t0 + j;
+        return z >= max(z0 - R * (L - j), -R) && z < min(z1 + R * (L - j), nz + R) && t >= -1 &&
+               t <= nt;
+    };
+    auto halo_src = [&](int j) {
+        const int t = t0 + j;
+        return LF ? (((t + 1) & 1) ? B1 : B0) : ((t & 1) ? B1 : B0);
+    };
 
-    // ---- register z-queues: q[j][c][i] = level j at plane z_j - 2R + i ------
+    // Value of level j at column c, plane z when it is held in memory (old
+    // frontier or boundary); 0 otherwise.
+    auto load_level = [&](int c, int j, int z) -> float {
+        const int code = classify(c, j, level_active(j, z), z >= 0 && z < nz);
+        const int64_t o = (int64_t)z * sz + off[c];
+        if (code == 1) return halo_src(j)[o];
+        if (code == 2) return FT[o];
+        if (code == 3) return FS[o];
+        return 0.0f;
+    };
+
+    // ---- register z-queues: qv[j][c][i] = level j at plane z_j - 2R + i ------
+    // With G0 level 0 (never computed here) has no queue: level 1 reads it
+    // from memory (cache) and its in-plane plane is prefetched.
     float qv[L][CPT][Q];
 #pragma unroll
     for (int j = 0; j < L; ++j)
@@ -128,117 +165,138 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
 #pragma unroll
             for (int i = 0; i < Q; ++i) qv[j][c][i] = 0.0f;
 
-    int lb = 0;  // LDS buffer toggle (uniform)
-    const int s_begin = z0 - R * (L + 1);
-    const int s_end = z1 + R * (L - 1);
-    for (int s = s_begin; s < s_end; ++s) {
-        // Recompute the per-column masks every step instead of keeping
-        // (levels x columns) loop-invariant masks alive in scalar registers.
+    // Values every level reads from memory (frontier or boundary) are loaded
+    // one stream step ahead: pf[j][c] for the next step, and for the
+    // leapfrog pp[c] = u_{t0-1} under level 1.
+    float pf[L + 1][CPT];
+    float pp[CPT];
+    auto prefetch = [&](int s) {
 #pragma unroll
         for (int c = 0; c < CPT; ++c) asm volatile("" : "+v"(info[c]));
 #pragma unroll
         for (int j = 0; j <= L; ++j) {
-            const int t = t0 + j;
+            // with G0, level 0 is prefetched at the plane level 1 reads in-plane
+            const int z = (G0 && j == 0) ? s : s - (j - 1) * R;
+            const bool za = level_active(j, z);
+            const bool zin = z >= 0 && z < nz;
+            const int64_t zo = (int64_t)z * sz;
+            const float* HB = halo_src(j);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int code = classify(c, j, za, zin);
+                float v = 0.0f;
+                if (code == 1) v = HB[zo + off[c]];
+                else if (code == 2) v = FT[zo + off[c]];
+                else if (code == 3) v = FS[zo + off[c]];
+                pf[j][c] = v;
+                if (LF && j == 1) pp[c] = (code == 4) ? FS[zo + off[c]] : 0.0f;
+            }
+        }
+    };
+
+    const int s_begin = z0 - R * (L + 1);
+    const int s_end = z1 + R * (L - 1);
+    prefetch(s_begin);
+    for (int s = s_begin; s < s_end; ++s) {
+        const int set = (s - s_begin) & 1;
+        float cur[L + 1][CPT];
+        float curp[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            curp[c] = pp[c];
+#pragma unroll
+            for (int j = 0; j <= L; ++j) cur[j][c] = pf[j][c];
+        }
+        if (s + 1 < s_end) prefetch(s + 1);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) asm volatile("" : "+v"(info[c]));
+#pragma unroll
+        for (int j = 0; j <= L; ++j) {
             const int z = s - (j - 1) * R;
-            // plane range of level j: [z0 - R(L-j), z1 + R(L-j)) within [-R, nz + R)
-            const bool zact = z >= max(z0 - R * (L - j), -R) && z < min(z1 + R * (L - j), nz + R) &&
-                              t >= -1 && t <= nt;
+            const bool za = level_active(j, z);
             const bool zin = z >= 0 && z < nz;
             const bool zout = z >= z0 && z < z1;
             const int64_t zo = (int64_t)z * sz;
-            const float* HB = LF ? (((t + 1) & 1) ? B1 : B0) : ((t & 1) ? B1 : B0);
-            bool cmp[CPT];
-            float val[CPT];
-            // 1. loads: frontier and boundary values of level j at plane z
+            const int jp = j >= 1 ? j - 1 : 0;
+            const float* P = lds[set][jp];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
-                cmp[c] = false;
-                val[c] = 0.0f;
-                const int jold = (int)(info[c] & 255u) - 64;
-                const int jnew = (int)((info[c] >> 8) & 255u) - 64;
-                const int jxm = (int)((info[c] >> 16) & 255u) - 64;
-                if (zact && (info[c] & (1u << 24)) && j <= jxm) {
-                    if (!((info[c] & (1u << 25)) && zin)) {
-                        val[c] = HB[zo + off[c]];
-                    } else if (j == jold) {
-                        val[c] = FT[zo + off[c]];
-                    } else if (j == jold - 1) {
-                        val[c] = FS[zo + off[c]];
-                    } else if (j > jold && j <= jnew) {
-                        cmp[c] = true;
+                const int code = classify(c, j, za, zin);
+                // with G0, cur[0] holds level 0 at the in-plane plane, not at z
+                float v = (G0 && j == 0) ? 0.0f : cur[j][c];
+                if (j >= 1 && code == 4) {
+                    float Wv[kslots<KIND>];
+                    Wv[0] = 0.0f;
+                    if constexpr (K > 0) {
+#pragma unroll
+                        for (int kk = 0; kk < K; ++kk) Wv[kk] = load_coef(W, kk * sk + zo + off[c]);
                     }
-                }
-            }
-            if (j >= 1) {
-                // 2. stage the centre plane (z) of level j-1 for in-plane neighbours
-                const int jp = j >= 1 ? j - 1 : 0;
-                float* P = lds[lb];
-#pragma unroll
-                for (int c = 0; c < CPT; ++c)
-                    if (wv + NWV * c < NCOL) P[lds_index(c)] = qv[jp][c][R];
-                __syncthreads();
-                // 3. compute
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    if (cmp[c]) {
-                        float Wv[kslots<KIND>];
-                        Wv[0] = 0.0f;
-                        if constexpr (K > 0) {
-#pragma unroll
-                            for (int kk = 0; kk < K; ++kk)
-                                Wv[kk] = load_coef(W, kk * sk + zo + off[c]);
-                        }
-                        float pv = 0.0f;
-                        if constexpr (LF) {
-                            if (j == 1)
-                                pv = FS[zo + off[c]];
-                            else
-                                pv = qv[j >= 2 ? j - 2 : 0][c][0];
-                        }
-                        const int li = lds_index(c);
-                        nbhd<R> n;
-                        n.c = qv[jp][c][R];
-#pragma unroll
-                        for (int r = 1; r <= R; ++r) {
-                            n.pair[0][r - 1] = P[li - r] + P[li + r];
-                            n.pair[1][r - 1] = P[li - r * XT] + P[li + r * XT];
-                            n.pair[2][r - 1] = qv[jp][c][R - r] + qv[jp][c][R + r];
-                        }
-                        n.m1[0] = P[li - 1];
-                        n.p1[0] = P[li + 1];
-                        n.m1[1] = P[li - XT];
-                        n.p1[1] = P[li + XT];
-                        n.m1[2] = qv[jp][c][R - 1];
-                        n.p1[2] = qv[jp][c][R + 1];
-                        val[c] = update<KIND>(wt, Wv, n, pv);
+                    float pv = 0.0f;
+                    if constexpr (LF) {
+                        if (j == 1)
+                            pv = curp[c];
+                        else if (G0 && j == 2)
+                            pv = load_level(c, 0, z);
+                        else
+                            pv = qv[j >= 2 ? j - 2 : 0][c][0];
                     }
-                    // keep one column's temporaries live at a time
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                lb ^= 1;
-            }
-            // 4. push into the queue of level j and write the new frontier
+                    const int li = lds_index(c);
+                    // z-neighbours of level j-1 at planes z-R .. z+R
+                    float zq[Q];
+                    if (G0 && j == 1) {
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                if (j < L) {
+                        for (int i = 0; i < Q; ++i) zq[i] = load_level(c, 0, z - R + i);
+                    } else {
 #pragma unroll
-                    for (int i = 0; i < Q - 1; ++i) qv[j < L ? j : 0][c][i] = qv[j < L ? j : 0][c][i + 1];
-                    qv[j < L ? j : 0][c][Q - 1] = val[c];
+                        for (int i = 0; i < Q; ++i) zq[i] = qv[jp][c][i];
+                    }
+                    nbhd<R> n;
+                    n.c = zq[R];
+#pragma unroll
+                    for (int r = 1; r <= R; ++r) {
+                        n.pair[0][r - 1] = P[li - r] + P[li + r];
+                        n.pair[1][r - 1] = P[li - r * XT] + P[li + r * XT];
+                        n.pair[2][r - 1] = zq[R - r] + zq[R + r];
+                    }
+                    n.m1[0] = P[li - 1];
+                    n.p1[0] = P[li + 1];
+                    n.m1[1] = P[li - XT];
+                    n.p1[1] = P[li + XT];
+                    n.m1[2] = zq[R - 1];
+                    n.p1[2] = zq[R + 1];
+                    v = update<KIND>(wt, Wv, n, pv);
                 }
-                if (zact && zout && (info[c] & (1u << 26))) {
+                if (j < L && !(G0 && j == 0)) {
+                    const int jq = j < L ? j : 0;
+#pragma unroll
+                    for (int i = 0; i < Q - 1; ++i) qv[jq][c][i] = qv[jq][c][i + 1];
+                    qv[jq][c][Q - 1] = v;
+                }
+                if (za && zout && (info[c] & (1u << 26))) {
                     const int jnew = (int)((info[c] >> 8) & 255u) - 64;
+                    if (G0 && j == 0 && (j == jnew || j == jnew - 1)) v = load_level(c, 0, z);
                     if (j == jnew)
-                        NT_[zo + off[c]] = val[c];
+                        NT_[zo + off[c]] = v;
                     else if (j == jnew - 1)
-                        NS[zo + off[c]] = val[c];
+                        NS[zo + off[c]] = v;
                 }
             }
         }
+        // Stage the planes the next step reads in-plane: level j-1 at plane
+        // z_j(s+1) sits at queue index R+1 now (it is R steps old).
+#pragma unroll
+        for (int j = 1; j <= L; ++j)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+                if (wv + NWV * c < NCOL)
+                    lds[set ^ 1][j - 1][lds_index(c)] =
+                        (G0 && j == 1) ? pf[0][c] : qv[j - 1][c][R + 1];
+        __syncthreads();
     }
 }
 
 // Register and LDS budget per (R, H): workgroup shape and columns per lane.
-template <int KIND, typename CT, int H, int NWV, int XCH>
+template <int KIND, typename CT, int H, int NWV, int XCH, bool G0 = false>
 hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
     constexpr int R = kind_traits<KIND>::R;
     const int ntiles = a.n_diamonds * a.gx * a.gz;
@@ -247,7 +305,7 @@ hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
     for (int i = 0; i < 5; ++i) wt.w[i] = a.wt.w[i];
     wt.alpha = a.wt.alpha;
     (void)R;
-    hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH>), dim3(ntiles), dim3(NWV * 64), 0,
+    hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, G0>), dim3(ntiles), dim3(NWV * 64), 0,
                        s, a.ftop_o, a.fsub_o, a.ftop_n, a.fsub_n, a.hb0, a.hb1,
                        static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.sy,
                        a.d.sz, a.d.org(), wt, (int)a.t0, (int)a.nt, a.first_centre, a.xo, a.gx,
@@ -262,9 +320,9 @@ hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
     if constexpr (R == 1) {
         if (H == 4) return launch_cfg<KIND, CT, 4, 10, 2>(a, s);
         if (H == 2) return launch_cfg<KIND, CT, 2, 6, 2>(a, s);
-        if (H == 6) return launch_cfg<KIND, CT, 6, 14, 2>(a, s);
+        if (H == 6) return launch_cfg<KIND, CT, 6, 7, 2>(a, s);
     } else {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 2>(a, s);
+        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 2, true>(a, s);
     }
     return hipErrorInvalidValue;
 }
