@@ -9,8 +9,10 @@ Every HIP translation unit is compiled with
 from __future__ import annotations
 
 import os
+import shutil
 import subprocess
 import sys
+import tempfile
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,9 +27,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={A
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-def _compile(src: str, build_dir: str) -> str:
+def _compile(src: str, src_dir: str, build_dir: str) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + ["-c", os.path.join(src_dir, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -37,11 +39,25 @@ def _compile(src: str, build_dir: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every translation unit and link libstencil.so.
+
+    hipcc reads a source file once for the device pass and once for the host
+    pass; compiling from a private snapshot of the sources guarantees that
+    both passes see the same text (an edit during a build could otherwise
+    give host launch stubs that name kernels the device code lacks).
+    """
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir), srcs))
+    snap = tempfile.mkdtemp(prefix="stencil_src_")
+    try:
+        shutil.copytree(CSRC, os.path.join(snap, "paper_1410_3060_amd", "csrc"))
+        shutil.copytree(os.path.join(os.path.dirname(HERE), "include"), os.path.join(snap, "include"))
+        src_dir = os.path.join(snap, "paper_1410_3060_amd", "csrc")
+        srcs = [s for s in SOURCES if os.path.exists(os.path.join(src_dir, s))]
+        with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+            objs = list(ex.map(lambda s: _compile(s, src_dir, build_dir), srcs))
+    finally:
+        shutil.rmtree(snap, ignore_errors=True)
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

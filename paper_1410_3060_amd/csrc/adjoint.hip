@@ -225,7 +225,7 @@ hipError_t launch_adjoint_step(bool bf16, const float* lam1, float* lam2, const 
         const long long txy = (long long)gx * gy;
         long long nzc = (2048 + txy - 1) / txy;
         zchunk = (int)((d.nz + nzc - 1) / nzc);
-        if (zchunk < 16 * R) zchunk = 16 * R;
+        if (zchunk < 4 * R) zchunk = 4 * R;
         if (zchunk > d.nz) zchunk = d.nz;
     }
     const int gz = (d.nz + zchunk - 1) / zchunk;

@@ -29,6 +29,7 @@
 // Boundary values (the shell of width halo) are always read from the caller's
 // buffer that holds that time level in the two-buffer convention.
 #include <algorithm>
+#include <type_traits>
 
 #include "blocked.h"
 #include "common.h"
@@ -38,7 +39,7 @@ namespace stn {
 
 namespace {
 
-template <int KIND, typename CT, int H, int NWV, int XCH, bool G0>
+template <int KIND, typename CT, int H, int NWV, int XCH, bool G0, bool CRING, int CG, int PD>
 __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const float* ftop_o, const float* fsub_o, float* ftop_n, float* fsub_n,
     const float* __restrict__ hb0, const float* __restrict__ hb1, const CT* __restrict__ coef,
@@ -79,6 +80,11 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const float* B0 = hb0 + cb;
     const float* B1 = hb1 + cb;
     const CT* W = coef ? coef + cb : nullptr;
+    // An always-valid element (the interior origin) for loads whose value is
+    // not needed: every load below is issued unconditionally so that no
+    // memory operation sits in divergent control flow, which keeps the
+    // hardware load counter exact and lets prefetches stay in flight.
+    const int64_t safe = -((int64_t)ybase * sy + xbase);
 
     // ---- per-column geometry, packed (fixed for the whole stream) -----------
     // off: yl*sy + xl.  info bits: [0,8) jold+64, [8,16) jnew+64, [16,24)
@@ -145,13 +151,15 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
 
     // Value of level j at column c, plane z when it is held in memory (old
     // frontier or boundary); 0 otherwise.
+    auto load_sel = [&](int code, int j, int64_t o) -> float {
+        const float* src = code == 1 ? halo_src(j) : (code == 3 ? FS : FT);
+        const bool mem = code >= 1 && code <= 3;
+        const float v = src[mem ? o : safe];
+        return mem ? v : 0.0f;
+    };
     auto load_level = [&](int c, int j, int z) -> float {
         const int code = classify(c, j, level_active(j, z), z >= 0 && z < nz);
-        const int64_t o = (int64_t)z * sz + off[c];
-        if (code == 1) return halo_src(j)[o];
-        if (code == 2) return FT[o];
-        if (code == 3) return FS[o];
-        return 0.0f;
+        return load_sel(code, j, (int64_t)z * sz + off[c]);
     };
 
     // ---- register z-queues: qv[j][c][i] = level j at plane z_j - 2R + i ------
@@ -165,12 +173,56 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
 #pragma unroll
             for (int i = 0; i < Q; ++i) qv[j][c][i] = 0.0f;
 
+    // ---- coefficient ring (CRING): the coefficients of plane z serve level j
+    // at step z + (j-1)R, so each column keeps the last NR = (L-1)R + 1 planes:
+    // cr[c][i][k] = coefficient k at plane s - i.  Loaded once per diamond,
+    // one step ahead (cp).  Without the ring, level j loads its coefficients
+    // from memory (cache) when it computes.
+    constexpr int NR = CRING ? (L - 1) * R + 1 : 1;
+    constexpr int KR = CRING ? kslots<KIND> : 1;
+    float cr[CPT][NR][KR];
+    // PD = prefetch depth in steps (1 or 2): the number of prefetch slots
+    float cp[PD][CPT][KR];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+#pragma unroll
+            for (int d = 0; d < PD; ++d) cp[d][c][k] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < NR; ++i) cr[c][i][k] = 0.0f;
+        }
+    // a column needs coefficients if it computes some level of this diamond
+    // and lies in level 1's x-range; planes of level 1's range, interior only
+    auto ring_load = [&](int s, auto slot) {
+        constexpr int SL = decltype(slot)::value;
+        if constexpr (CRING) {
+            const bool zok = s >= 0 && s < nz && s >= z0 - R * (L - 1) && s < z1 + R * (L - 1);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const uint32_t f = info[c];
+                const int jold = (int)(f & 255u) - 64;
+                const int jnew = (int)((f >> 8) & 255u) - 64;
+                const int jxm = (int)((f >> 16) & 255u) - 64;
+                const bool need = zok && (f & (1u << 24)) && (f & (1u << 25)) && jnew > jold &&
+                                  jxm >= 1;
+#pragma unroll
+                for (int k = 0; k < KR; ++k) {
+                    const float v = load_coef(W, need ? k * sk + (int64_t)s * sz + off[c] : safe);
+                    cp[SL][c][k] = need ? v : 0.0f;
+                }
+            }
+        }
+    };
+
     // Values every level reads from memory (frontier or boundary) are loaded
-    // one stream step ahead: pf[j][c] for the next step, and for the
-    // leapfrog pp[c] = u_{t0-1} under level 1.
-    float pf[L + 1][CPT];
-    float pp[CPT];
-    auto prefetch = [&](int s) {
+    // two stream steps ahead, into slot s % 2: pf[slot][j][c], and for the
+    // leapfrog pp[slot][c] = u_{t0-1} under level 1.  The stream loop is
+    // unrolled by two so that the slots stay registers.
+    float pf[PD][L + 1][CPT];
+    float pp[PD][CPT];
+    auto prefetch = [&](int s, auto slot) {
+        constexpr int SL = decltype(slot)::value;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) asm volatile("" : "+v"(info[c]));
 #pragma unroll
@@ -180,34 +232,47 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             const bool za = level_active(j, z);
             const bool zin = z >= 0 && z < nz;
             const int64_t zo = (int64_t)z * sz;
-            const float* HB = halo_src(j);
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
                 const int code = classify(c, j, za, zin);
-                float v = 0.0f;
-                if (code == 1) v = HB[zo + off[c]];
-                else if (code == 2) v = FT[zo + off[c]];
-                else if (code == 3) v = FS[zo + off[c]];
-                pf[j][c] = v;
-                if (LF && j == 1) pp[c] = (code == 4) ? FS[zo + off[c]] : 0.0f;
+                pf[SL][j][c] = load_sel(code, j, zo + off[c]);
+                if (LF && j == 1) {
+                    const float v = FS[code == 4 ? zo + off[c] : safe];
+                    pp[SL][c] = code == 4 ? v : 0.0f;
+                }
             }
         }
+        ring_load(s, slot);
     };
 
     const int s_begin = z0 - R * (L + 1);
     const int s_end = z1 + R * (L - 1);
-    prefetch(s_begin);
-    for (int s = s_begin; s < s_end; ++s) {
-        const int set = (s - s_begin) & 1;
+    prefetch(s_begin, std::integral_constant<int, 0>{});
+    if (PD == 2 && s_begin + 1 < s_end) prefetch(s_begin + 1, std::integral_constant<int, PD - 1>{});
+    auto step = [&](int s, auto par) {
+        constexpr int set = decltype(par)::value;  // LDS set read by step s: parity of s - s_begin
+        constexpr int SL = PD == 2 ? set : 0;      // prefetch slot holding step s
         float cur[L + 1][CPT];
         float curp[CPT];
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            curp[c] = pp[c];
+            curp[c] = pp[SL][c];
 #pragma unroll
-            for (int j = 0; j <= L; ++j) cur[j][c] = pf[j][c];
+            for (int j = 0; j <= L; ++j) cur[j][c] = pf[SL][j][c];
+            if constexpr (CRING) {
+#pragma unroll
+                for (int i = NR - 1; i > 0; --i)
+#pragma unroll
+                    for (int k = 0; k < KR; ++k) cr[c][i][k] = cr[c][i - 1][k];
+#pragma unroll
+                for (int k = 0; k < KR; ++k) cr[c][0][k] = cp[SL][c][k];
+            }
         }
-        if (s + 1 < s_end) prefetch(s + 1);
+        if constexpr (PD == 2) {
+            if (s + 2 < s_end) prefetch(s + 2, std::integral_constant<int, SL>{});
+        } else {
+            if (s + 1 < s_end) prefetch(s + 1, std::integral_constant<int, 0>{});
+        }
 #pragma unroll
         for (int c = 0; c < CPT; ++c) asm volatile("" : "+v"(info[c]));
 #pragma unroll
@@ -219,52 +284,84 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             const int64_t zo = (int64_t)z * sz;
             const int jp = j >= 1 ? j - 1 : 0;
             const float* P = lds[set][jp];
+            int code[CPT];
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int code = classify(c, j, za, zin);
-                // with G0, cur[0] holds level 0 at the in-plane plane, not at z
-                float v = (G0 && j == 0) ? 0.0f : cur[j][c];
-                if (j >= 1 && code == 4) {
-                    float Wv[kslots<KIND>];
-                    Wv[0] = 0.0f;
-                    if constexpr (K > 0) {
+            for (int c = 0; c < CPT; ++c) code[c] = classify(c, j, za, zin);
+            // Columns are processed in groups of CG: phase 1 issues every memory
+            // read of the group's updates, phase 2 consumes them, so one memory
+            // round trip serves CG columns while only CG columns' operands are live.
 #pragma unroll
-                        for (int kk = 0; kk < K; ++kk) Wv[kk] = load_coef(W, kk * sk + zo + off[c]);
+            for (int g0 = 0; g0 < CPT; g0 += CG) {
+            // phase 1: every memory read of this level for the group, before any use
+            float Wv[CG][kslots<KIND>];
+            float zq[CG][Q];
+            float pv[CG];
+#pragma unroll
+            for (int cc = 0; cc < CG; ++cc) {
+                const int c = g0 + cc < CPT ? g0 + cc : CPT - 1;
+#pragma unroll
+                for (int k = 0; k < kslots<KIND>; ++k) Wv[cc][k] = 0.0f;
+                pv[cc] = 0.0f;
+                const bool cmp = g0 + cc < CPT && j >= 1 && code[c] == 4;
+                if constexpr (K > 0 && !CRING) {
+                    if (j >= 1) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            Wv[cc][k] = load_coef(W, cmp ? k * sk + zo + off[c] : safe);
                     }
-                    float pv = 0.0f;
+                }
+                if (cmp) {
+                    if constexpr (K > 0 && CRING) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k) Wv[cc][k] = cr[c][(j >= 1 ? j - 1 : 0) * R][k];
+                    }
                     if constexpr (LF) {
                         if (j == 1)
-                            pv = curp[c];
-                        else if (G0 && j == 2)
-                            pv = load_level(c, 0, z);
-                        else
-                            pv = qv[j >= 2 ? j - 2 : 0][c][0];
+                            pv[cc] = curp[c];
+                        else if (!(G0 && j == 2))
+                            pv[cc] = qv[j >= 2 ? j - 2 : 0][c][0];
                     }
+                }
+                // level 0 operands from memory (G0): issued for every column
+                if constexpr (G0 && LF) {
+                    if (j == 2) {
+                        const float v = load_level(c, 0, z);
+                        if (cmp) pv[cc] = v;
+                    }
+                }
+                if (G0 && j == 1) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) zq[cc][i] = load_level(c, 0, z - R + i);
+                }
+                if (!(G0 && j == 1)) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) zq[cc][i] = qv[jp][c][i];
+                }
+            }
+            // phase 2: compute, push, write back
+#pragma unroll
+            for (int cc = 0; cc < CG; ++cc) {
+                const int c = g0 + cc < CPT ? g0 + cc : CPT - 1;
+                if (g0 + cc >= CPT) continue;
+                // with G0, cur[0] holds level 0 at the in-plane plane, not at z
+                float v = (G0 && j == 0) ? 0.0f : cur[j][c];
+                if (j >= 1 && code[c] == 4) {
                     const int li = lds_index(c);
-                    // z-neighbours of level j-1 at planes z-R .. z+R
-                    float zq[Q];
-                    if (G0 && j == 1) {
-#pragma unroll
-                        for (int i = 0; i < Q; ++i) zq[i] = load_level(c, 0, z - R + i);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < Q; ++i) zq[i] = qv[jp][c][i];
-                    }
                     nbhd<R> n;
-                    n.c = zq[R];
+                    n.c = zq[cc][R];
 #pragma unroll
                     for (int r = 1; r <= R; ++r) {
                         n.pair[0][r - 1] = P[li - r] + P[li + r];
                         n.pair[1][r - 1] = P[li - r * XT] + P[li + r * XT];
-                        n.pair[2][r - 1] = zq[R - r] + zq[R + r];
+                        n.pair[2][r - 1] = zq[cc][R - r] + zq[cc][R + r];
                     }
                     n.m1[0] = P[li - 1];
                     n.p1[0] = P[li + 1];
                     n.m1[1] = P[li - XT];
                     n.p1[1] = P[li + XT];
-                    n.m1[2] = zq[R - 1];
-                    n.p1[2] = zq[R + 1];
-                    v = update<KIND>(wt, Wv, n, pv);
+                    n.m1[2] = zq[cc][R - 1];
+                    n.p1[2] = zq[cc][R + 1];
+                    v = update<KIND>(wt, Wv[cc], n, pv[cc]);
                 }
                 if (j < L && !(G0 && j == 0)) {
                     const int jq = j < L ? j : 0;
@@ -272,14 +369,17 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                     for (int i = 0; i < Q - 1; ++i) qv[jq][c][i] = qv[jq][c][i + 1];
                     qv[jq][c][Q - 1] = v;
                 }
+                if (G0 && j == 0) v = load_level(c, 0, z);  // only written back, rarely
                 if (za && zout && (info[c] & (1u << 26))) {
                     const int jnew = (int)((info[c] >> 8) & 255u) - 64;
-                    if (G0 && j == 0 && (j == jnew || j == jnew - 1)) v = load_level(c, 0, z);
                     if (j == jnew)
                         NT_[zo + off[c]] = v;
                     else if (j == jnew - 1)
                         NS[zo + off[c]] = v;
                 }
+            }
+            // keep the next group's loads from being hoisted above this one
+            if constexpr (CG < CPT) __builtin_amdgcn_sched_barrier(0);
             }
         }
         // Stage the planes the next step reads in-plane: level j-1 at plane
@@ -290,13 +390,18 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             for (int c = 0; c < CPT; ++c)
                 if (wv + NWV * c < NCOL)
                     lds[set ^ 1][j - 1][lds_index(c)] =
-                        (G0 && j == 1) ? pf[0][c] : qv[j - 1][c][R + 1];
+                        (G0 && j == 1) ? pf[PD == 2 ? SL ^ 1 : 0][0][c] : qv[j - 1][c][R + 1];
         __syncthreads();
+    };
+    for (int s = s_begin; s < s_end; s += 2) {
+        step(s, std::integral_constant<int, 0>{});
+        if (s + 1 < s_end) step(s + 1, std::integral_constant<int, 1>{});
     }
 }
 
 // Register and LDS budget per (R, H): workgroup shape and columns per lane.
-template <int KIND, typename CT, int H, int NWV, int XCH, bool G0 = false>
+template <int KIND, typename CT, int H, int NWV, int XCH, bool G0 = false, bool CRING = false,
+          int CG = 8, int PD = 2>
 hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
     constexpr int R = kind_traits<KIND>::R;
     const int ntiles = a.n_diamonds * a.gx * a.gz;
@@ -305,7 +410,7 @@ hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
     for (int i = 0; i < 5; ++i) wt.w[i] = a.wt.w[i];
     wt.alpha = a.wt.alpha;
     (void)R;
-    hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, G0>), dim3(ntiles), dim3(NWV * 64), 0,
+    hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, G0, CRING, CG, PD>), dim3(ntiles), dim3(NWV * 64), 0,
                        s, a.ftop_o, a.fsub_o, a.ftop_n, a.fsub_n, a.hb0, a.hb1,
                        static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.sy,
                        a.d.sz, a.d.org(), wt, (int)a.t0, (int)a.nt, a.first_centre, a.xo, a.gx,
@@ -313,19 +418,32 @@ hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Workgroup shape per (kind, H): waves, 64-lane x chunks, level 0 read from
+// cache (G0), coefficient ring in registers (CRING).  Register budget per
+// column: L z-queues of 2R+1 values, plus (L-1)R+1 coefficient planes of K
+// values with the ring.
 template <int KIND, typename CT>
 hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
     constexpr int R = kind_traits<KIND>::R;
     const int H = a.dw / (2 * R);
-    if constexpr (R == 1) {
-        if (H == 4) return launch_cfg<KIND, CT, 4, 10, 2>(a, s);
+    if constexpr (KIND == 1) {
         if (H == 2) return launch_cfg<KIND, CT, 2, 6, 2>(a, s);
+        if (H == 4) return launch_cfg<KIND, CT, 4, 10, 2>(a, s);
         if (H == 6) return launch_cfg<KIND, CT, 6, 7, 2>(a, s);
+    } else if constexpr (KIND == 2) {
+        if (H == 2) return launch_cfg<KIND, CT, 2, 6, 2, false, true>(a, s);
+        if (H == 4) return launch_cfg<KIND, CT, 4, 10, 1, false, true>(a, s);
+        if (H == 6) return launch_cfg<KIND, CT, 6, 7, 2>(a, s);
+    } else if constexpr (KIND == 5) {
+        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 2, true, false, 1, 1>(a, s);
     } else {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 2, true>(a, s);
+        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 2, true, false, 1, 1>(a, s);
     }
     return hipErrorInvalidValue;
 }
+
+// x chunks of the configuration above (host side)
+int cfg_xch(int kind, int H) { return (kind == 2 && H == 4) ? 1 : 2; }
 
 }  // namespace
 
@@ -340,8 +458,9 @@ int blocked_default_dw(int kind) { return (kind == 1 || kind == 2) ? 8 : 16; }
 
 int blocked_max_xo(int kind, int dw) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;
-    const int L = dw / R - 1;
-    return 128 - 2 * R * L;
+    const int H = dw / (2 * R);
+    const int L = 2 * H - 1;
+    return 64 * cfg_xch(kind, H) - 2 * R * L;
 }
 
 hipError_t launch_blocked_row(int kind, bool bf16, const blocked_row_args& a, hipStream_t s) {

@@ -202,11 +202,12 @@ int naive_default_zchunk(int kind, const dims& d) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;
     const int TY = NW * (R == 1 ? 8 : 4);
     const long long txy = (long long)((d.nx + 63) / 64) * ((d.ny + TY - 1) / TY);
-    // aim at >= 2048 workgroups (8 per CU) with chunks of at least 16R planes
+    // aim at >= 2048 workgroups (8 per CU) with chunks of at least 4R planes
+    // (a chunk re-reads 2R planes of the stencil operand, mostly from L2)
     long long nzc = (2048 + txy - 1) / (txy > 0 ? txy : 1);
     if (nzc < 1) nzc = 1;
     int zc = (int)((d.nz + nzc - 1) / nzc);
-    if (zc < 16 * R) zc = 16 * R;
+    if (zc < 4 * R) zc = 4 * R;
     if (zc > d.nz) zc = d.nz > 0 ? d.nz : 1;
     return zc;
 }
