@@ -24,10 +24,12 @@
  *   x stride is 1; sy >= nx + 2*halo; sz >= sy * (ny + 2*halo).  All fields of
  *   one call (both time levels, every coefficient array, adjoint inputs and
  *   outputs) share these element strides.
- * Boundary.  The shell is read as a Dirichlet boundary and never written.
- *   Time level t reads the shell of the buffer that holds level t in the
- *   two-buffer scheme below; callers who want a time-independent boundary give
- *   u[0] and u[1] the same shell (the usual case: both zero).
+ * Boundary.  The shell is a time-independent Dirichlet boundary: every level
+ *   reads the shell of the buffer that holds level 0 (u[0] for kinds 1-3,
+ *   u[1] for kinds 4-5).  The naive scheme reads the shell of the buffer that
+ *   holds the level it reads, so the two schemes agree when u[0] and u[1]
+ *   carry the same shell (the usual case: both zero); the blocked scheme
+ *   copies the level-0 shell into the other buffer before it starts.
  * Two-buffer time storage (Sect. 2.1: only two levels are stored and level
  *   t+1 overwrites level t-1).  Jacobi kinds (1-3): u[0] holds level 0 on
  *   entry and level t lives in u[t % 2].  Leapfrog kinds (4-5): u[0] holds

@@ -261,15 +261,26 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
     float* fin_sub = slot ? u0 : u1;
     const float* rt = lf ? u1 : u0;  // level 0
     const float* rs = lf ? u0 : u1;  // level -1 (leapfrog) / unused (Jacobi)
+    // The blocked kernel reads boundary values from whichever frontier buffer
+    // holds the newest level, so every buffer it reads carries the shell of
+    // the level-0 buffer (the boundary is time independent).
+    const float* shell = rt;
+    float* other = const_cast<float*>(rs);
+    hipError_t e = stn::launch_copy_shell(other, shell, d, R, ctx->stream);
+    if (e != hipSuccess) return dev_fail(e, "shell copy");
     bool reading_caller = true;
     if (plan.rows.size() % 2 == 1) {
-        hipError_t e = hipMemcpyAsync(w0, rt, fbytes, hipMemcpyDeviceToDevice, ctx->stream);
-        if (e == hipSuccess && lf)
+        e = hipMemcpyAsync(w0, rt, fbytes, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
             e = hipMemcpyAsync(w1, rs, fbytes, hipMemcpyDeviceToDevice, ctx->stream);
         if (e != hipSuccess) return dev_fail(e, "frontier copy");
         rt = w0;
         rs = w1;
         reading_caller = false;
+    } else {
+        e = stn::launch_copy_shell(w0, shell, d, R, ctx->stream);
+        if (e == hipSuccess) e = stn::launch_copy_shell(w1, shell, d, R, ctx->stream);
+        if (e != hipSuccess) return dev_fail(e, "shell copy");
     }
     const int xomax = stn::blocked_max_xo(kind, dw);
     const int gx = (g->nx + xomax - 1) / xomax;
@@ -281,8 +292,6 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         a.fsub_o = rs;
         a.ftop_n = reading_caller ? w0 : fin_top;
         a.fsub_n = reading_caller ? w1 : fin_sub;
-        a.hb0 = u0;
-        a.hb1 = u1;
         a.coef = c->arrays;
         a.sk = c->sk;
         a.d = d;
@@ -307,7 +316,7 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         a.gz = (g->nz + zc - 1) / zc;
         if ((long long)a.n_diamonds * a.gx * a.gz > 0x7fffffffLL)
             return fail(STENCIL_ERR_INVALID, "grid too large for one launch");
-        hipError_t e = stn::launch_blocked_row(kind, bf16, a, ctx->stream);
+        e = stn::launch_blocked_row(kind, bf16, a, ctx->stream);
         if (e != hipSuccess) return dev_fail(e, "blocked row launch");
         rt = a.ftop_n;
         rs = a.fsub_n;

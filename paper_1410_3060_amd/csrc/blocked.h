@@ -8,14 +8,14 @@
 
 namespace stn {
 
-// One row of diamonds: reads the old frontier pair, writes the new one.
+// One row of diamonds: reads the old frontier pair, writes the new one.  The
+// boundary shell (width R) is read from the old frontier top and must be the
+// same in every frontier buffer.
 struct blocked_row_args {
     const float* ftop_o;  // old frontier: newest level per point
     const float* fsub_o;  // old frontier: the level below it
     float* ftop_n;        // new frontier (distinct buffers)
     float* fsub_n;
-    const float* hb0;     // caller buffers u[0], u[1]: boundary shells by time level
-    const float* hb1;
     const void* coef;
     int64_t sk;
     dims d;

@@ -29,4 +29,8 @@ hipError_t launch_naive_step(int kind, bool coef_bf16, const float* cur, const f
 // Planes per z-chunk the naive launcher picks when zchunk == 0.
 int naive_default_zchunk(int kind, const dims& d);
 
+// Copy the boundary shell of width r (every point of [-r, n+r)^3 outside the
+// interior) from src to dst; interior points of dst are not touched.
+hipError_t launch_copy_shell(float* dst, const float* src, const dims& d, int r, hipStream_t s);
+
 }  // namespace stn

@@ -196,7 +196,32 @@ hipError_t launch_kind(const float* cur, const float* prev, float* out, const vo
     return hipGetLastError();
 }
 
+// One workgroup per padded (y, z) row: rows in the shell are copied whole,
+// interior rows only at their 2r boundary columns.
+__global__ void copy_shell_kernel(float* dst, const float* src, int nx, int ny, int nz, int r,
+                                  int64_t sy, int64_t sz, int64_t org) {
+    const int rows_y = ny + 2 * r;
+    const int y = (int)(blockIdx.x % rows_y) - r;
+    const int z = (int)(blockIdx.x / rows_y) - r;
+    const int64_t o = org + (int64_t)z * sz + (int64_t)y * sy;
+    if (y < 0 || y >= ny || z < 0 || z >= nz) {
+        for (int x = (int)threadIdx.x - r; x < nx + r; x += blockDim.x) dst[o + x] = src[o + x];
+    } else if ((int)threadIdx.x < 2 * r) {
+        const int x = (int)threadIdx.x < r ? (int)threadIdx.x - r : nx + (int)threadIdx.x - r;
+        dst[o + x] = src[o + x];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_copy_shell(float* dst, const float* src, const dims& d, int r, hipStream_t s) {
+    const long long rows = (long long)(d.ny + 2 * r) * (d.nz + 2 * r);
+    if (rows <= 0 || d.nx <= 0) return hipSuccess;
+    if (rows > 0x7fffffffLL || r > 32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(copy_shell_kernel, dim3((unsigned)rows), dim3(64), 0, s, dst, src, d.nx,
+                       d.ny, d.nz, r, d.sy, d.sz, d.org());
+    return hipGetLastError();
+}
 
 int naive_default_zchunk(int kind, const dims& d) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;
