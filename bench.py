@@ -135,8 +135,12 @@ def main():
     # average row-launch duration from the same HIP events (launch gaps included)
     avg_launch = t_step / n_rows
     achieved = bpl_b * lups / n_rows / avg_launch / 1e9
+    traffic = measured_traffic(wl.name, args.dw)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
+                "algorithmic_per_launch_GB": round(bpl_b * lups / n_rows / 1e9, 3),
                 "copy_probe_GBps": probe["GBps"],
                 "kernel": "blocked_row_kernel<3,float,H=%d>" % H,
                 "bytes_per_lup": round(bpl_b, 3), "avg_launch_ms": round(avg_launch * 1e3, 4)}
@@ -196,6 +200,31 @@ def main():
         "extras": extras,
     }
     print(json.dumps(line), flush=True)
+
+
+KERNEL_SOURCES = ["paper_1410_3060_amd/csrc/blocked.hip", "paper_1410_3060_amd/csrc/blocked.h",
+                  "paper_1410_3060_amd/csrc/point_ops.h", "paper_1410_3060_amd/csrc/common.h",
+                  "paper_1410_3060_amd/csrc/kernels.h"]
+
+
+def measured_traffic(workload, dw):
+    """HBM bytes per launch of the blocked kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since the
+    counters were taken (or they were taken on another workload)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))["blocked_row_kernel"]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec.get("sources", KERNEL_SOURCES):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("source_sha256") or rec.get("workload") != workload or \
+            rec.get("dw") != dw:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
 
 
 def copy_probe(torch, nbytes=1 << 32, reps=10):
@@ -271,29 +300,36 @@ def adjoint_leg(st, workloads, torch, np, stream, args):
 
 
 def cpu_leg(wl, seconds):
-    """The FP64 oracle on a bounded sample of the workload, on all host cores."""
+    """The FP64 oracle on a bounded sample of the workload, on all host cores.
+
+    The sample is the full seeded grid run for as many of the workload's time
+    steps as fit in about `seconds` (one calibration step first); if a single
+    step already takes longer, the leading planes of the grid instead."""
     import numpy as np
 
     import oracle
-    # sample: the leading nz_s planes of the same seeded grid, a few steps,
-    # sized from a short calibration to take about `seconds`
     h = wl.halo
     nx, ny, nz = wl.n3
-    nz_s = min(nz, 96)
-    sl = slice(0, nz_s + 2 * h)
-    u = np.ascontiguousarray(wl.u0[sl], dtype=np.float64)
-    cf = np.ascontiguousarray(wl.coef[:, sl], dtype=np.float64)
+    u = np.asarray(wl.u0, dtype=np.float64)
+    cf = np.asarray(wl.coef, dtype=np.float64)
     t = []
     oracle.run(wl.kind, u, h, 1, coef=cf, timing=t)
     per_step = max(t[0], 1e-3)
-    nt_s = int(max(1, min(100, seconds / per_step)))
+    nz_s = nz
+    if per_step > seconds / 4:
+        nz_s = max(2 * h, int(nz * seconds / 4 / per_step))
+        sl = slice(0, nz_s + 2 * h)
+        u = np.ascontiguousarray(u[sl])
+        cf = np.ascontiguousarray(cf[:, sl])
+        per_step *= nz_s / nz
+    nt_s = int(max(1, min(wl.nt, seconds / per_step)))
     t = []
     oracle.run(wl.kind, u, h, nt_s, coef=cf, timing=t)
     secs = t[0]
     glups = nx * ny * nz_s * nt_s / secs / 1e9
     return {"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.max_threads(),
             "kind": "oracle",
-            "sample": f"{nx}x{ny}x{nz_s} slab of the same seeded grid, {nt_s} steps, FP64, "
+            "sample": f"{nx}x{ny}x{nz_s} of the same seeded grid, {nt_s} of {wl.nt} steps, FP64, "
                       f"{secs:.1f} s", "host_cpus": os.cpu_count()}
 
 
