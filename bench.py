@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--n", type=int, default=None, help="override the grid size (testing only)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the adjoint leg (forward with checkpoints, then the adjoint)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the device-to-device copy probe and print its bandwidth")
     args = ap.parse_args()
@@ -84,6 +86,10 @@ def main():
     probe = copy_probe(torch)
     if args.copy_probe:
         print(json.dumps({"copy_probe": probe}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(st, workloads, torch, np, stream, args)}),
+              flush=True)
         return
 
     t_gen = time.time()

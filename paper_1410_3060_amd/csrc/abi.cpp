@@ -460,10 +460,31 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
         for (int64_t i = 1; i + a < b && e == hipSuccess; ++i)
             e = stn::launch_naive_step(5, bf16, slot((int)i), slot((int)i - 1), slot((int)i + 1),
                                        c->arrays, c->sk, d, wt, 0, st);
-        for (int64_t s = b - 1; s >= a && e == hipSuccess; --s) {
-            e = stn::launch_adjoint_step(bf16, cur, nxt, c->arrays, slot((int)(s - a + 1)), g_c, d,
-                                         w, 0, st);
+        // reverse steps b-1 .. a in groups of three: the middle step of a
+        // group also adds the gradient terms of its two neighbours, so the
+        // FP64 gradient is read and written once per group
+        auto U = [&](int64_t n) -> const float* { return slot((int)(n - a + 1)); };
+        auto step = [&](const float* up, const float* uc, const float* un) {
+            hipError_t r = stn::launch_adjoint_step(bf16, cur, nxt, c->arrays, up, uc, un, g_c, d,
+                                                    w, 0, st);
             std::swap(cur, nxt);
+            return r;
+        };
+        for (int64_t s = b - 1; s >= a && e == hipSuccess;) {
+            const int64_t left = s - a + 1;
+            if (left >= 3) {
+                e = step(nullptr, nullptr, nullptr);
+                if (e == hipSuccess) e = step(U(s), U(s - 1), U(s - 2));
+                if (e == hipSuccess) e = step(nullptr, nullptr, nullptr);
+                s -= 3;
+            } else if (left == 2) {
+                e = step(nullptr, nullptr, nullptr);
+                if (e == hipSuccess) e = step(U(s), U(s - 1), nullptr);
+                s -= 2;
+            } else {
+                e = step(nullptr, U(s), nullptr);
+                s -= 1;
+            }
         }
     }
     if (e == hipSuccess) e = stn::launch_scale_copy(g_u0, cur, 1.0f, d, st);

@@ -8,12 +8,15 @@
 
 namespace stn {
 
-// One reverse step of the leapfrog with c(x): lam2 <- 2 lam1 - lam2 + L8(c lam1)
-// (lam1 = lambda_{n+1}, lam2 = lambda_{n+2} on entry and lambda_n on return)
-// and g += lam1 * L8(us) in FP64 (us = u_n).  w: the five L8 weights.
+// One reverse step m of the leapfrog with c(x):
+//   lam2 <- 2 lam1 - lam2 + L8(c lam1)
+// (lam1 = lambda_{m+1}, lam2 = lambda_{m+2} on entry and lambda_m on return),
+// and, in FP64, g += lambda_{m+2} L8(u_p) + lambda_{m+1} L8(u_c) + lambda_m L8(u_n)
+// for the u fields given (u_p = u_{m+1}, u_c = u_m, u_n = u_{m-1}; null
+// pointers drop their term, all null leaves g untouched).  w: the five L8 weights.
 hipError_t launch_adjoint_step(bool coef_bf16, const float* lam1, float* lam2, const void* coef,
-                               const float* us, double* g, const dims& d, const double* w,
-                               int zchunk, hipStream_t s);
+                               const float* u_p, const float* u_c, const float* u_n, double* g,
+                               const dims& d, const double* w, int zchunk, hipStream_t s);
 
 // Interior-only helpers (the boundary shell of dst is never written).
 hipError_t launch_scale_copy(float* dst, const float* src, float a, const dims& d, hipStream_t s);

@@ -7,13 +7,22 @@
 //           g_c     += lambda_{n+1} * L8(u_n)          (accumulated in FP64)
 // with L8 symmetric on the interior (zero outside for the adjoint fields).
 //
-// One launch performs one reverse step for all points, fused: a 2.5D stream
-// along z like the naive sweep, with two stencil operands (v = c * lambda_{n+1}
-// and u_n), each held as a register z-queue plus an LDS plane.  lambda_n
-// overwrites lambda_{n+2} in place (each point reads its own old value
-// first), so two lambda buffers suffice.  The gradient term uses an FP64
-// evaluation of L8(u_n) from the FP32 values, so that the cancellation inside
-// the stencil sum does not cost FP32 digits in the coefficient gradient.
+// One launch performs one reverse step m for all points: a 2.5D stream along
+// z like the naive sweep, with the stencil operand v = c * lambda_{m+1} held
+// as a register z-queue plus an LDS plane, every operand of the next plane
+// loaded while the current one is computed.  lambda_m overwrites
+// lambda_{m+2} in place (each point reads its own old value first), so two
+// lambda buffers suffice.
+//
+// The gradient update is the costly part of a step in memory traffic (an
+// FP64 read and write per point), so a launch may fold in the gradient terms
+// of up to three consecutive steps and the steps around it carry none.  At
+// step m the launch knows lambda_{m+2}, lambda_{m+1} and lambda_m, which are
+// the multipliers of the terms of steps m+1, m and m-1:
+//     g += lambda_{m+2} L8(u_{m+1}) + lambda_{m+1} L8(u_m) + lambda_m L8(u_{m-1})
+// (TERMS selects which are present).  Each L8(u) is evaluated in FP64 from the
+// FP32 values, so that the cancellation inside the stencil sum does not cost
+// FP32 digits in the coefficient gradient.
 #include "adjoint.h"
 #include "common.h"
 #include "point_ops.h"
@@ -31,16 +40,21 @@ struct w64 {
     double w[5];
 };
 
-template <typename CT, int RPT>
+// TERMS: bit 0 the term of step m+1, bit 1 of step m, bit 2 of step m-1.
+template <typename CT, int RPT, int TERMS>
 __global__ __launch_bounds__(NT) void adjoint_step_kernel(
     const float* __restrict__ lam1, float* lam2, const CT* __restrict__ coef,
-    const float* __restrict__ us, double* __restrict__ g, int nx, int ny, int nz, int64_t sy,
-    int64_t sz, int64_t org, weights wt, w64 wd, int zchunk, int gx, int gy, int ntiles) {
+    const float* u_p, const float* u_c, const float* u_n, double* __restrict__ g, int nx, int ny,
+    int nz, int64_t sy, int64_t sz, int64_t org, weights wt, w64 wd, int zchunk, int gx, int gy,
+    int ntiles) {
+    constexpr int NU = (TERMS & 1) + ((TERMS >> 1) & 1) + ((TERMS >> 2) & 1);
+    constexpr int NUA = NU > 0 ? NU : 1;
+    constexpr int F = 1 + NU;  // LDS planes: v, then the u fields
     constexpr int TY = NW * RPT;
     constexpr int LW = 64 + 2 * R;
     constexpr int LH = TY + 2 * R;
-    __shared__ float ldv[2][LH][LW];
-    __shared__ float ldu[2][LH][LW];
+    constexpr int HYJ = (2 * R + NW - 1) / NW;
+    __shared__ float lds[F][2][LH][LW];
 
     const int tile = xcd_remap(blockIdx.x, ntiles);
     const int bx = tile % gx;
@@ -56,124 +70,194 @@ __global__ __launch_bounds__(NT) void adjoint_step_kernel(
     const float* L1 = lam1 + org;
     float* L2 = lam2 + org;
     const CT* C = coef + org;
-    const float* U = us + org;
     double* G = g + org;
+    const float* U[NUA];
+    {
+        int f = 0;
+        if constexpr ((TERMS & 1) != 0) U[f++] = u_p + org;
+        if constexpr ((TERMS & 2) != 0) U[f++] = u_c + org;
+        if constexpr ((TERMS & 4) != 0) U[f++] = u_n + org;
+        if constexpr (NU == 0) U[0] = nullptr;
+    }
 
-    // v = c * lambda on the interior, 0 on the boundary shell
-    auto vload = [&](int64_t zo, int64_t co, int xx, int yy, int zz) -> float {
-        const bool in = xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz;
-        return in ? load_coef(C, zo + co) * L1[zo + co] : 0.0f;
-    };
-
-    int64_t colo[RPT];
-    int ys[RPT];
-    bool ld_ok[RPT], st_ok[RPT];
+    // Points a lane loads: its RPT columns, its share of the 2R y-halo rows
+    // and (first 2R*TY threads) one x-halo point.  Loads that are not needed
+    // read the interior origin instead, so that no load sits in a branch.
+    int64_t co[RPT];
+    bool cin[RPT], cld[RPT], cst[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int y = y0 + wv + NW * i;
-        ys[i] = y;
-        colo[i] = (int64_t)y * sy + x;
-        ld_ok[i] = (x < nx + R) && (y < ny + R);
-        st_ok[i] = (x < nx) && (y < ny);
+        co[i] = (int64_t)y * sy + x;
+        cin[i] = x < nx && y < ny;
+        cld[i] = x < nx + R && y < ny + R;
+        cst[i] = cin[i];
     }
-    constexpr int HYJ = (2 * R + NW - 1) / NW;
-    int64_t hyo[HYJ];
-    int hy_y[HYJ], hy_row[HYJ];
-    bool hy_ok[HYJ];
+    int64_t ho[HYJ];
+    bool hin[HYJ], hld[HYJ];
+    int hrow[HYJ];
 #pragma unroll
     for (int j = 0; j < HYJ; ++j) {
         const int hr = wv + NW * j;
         const int ly = hr < R ? hr - R : TY + (hr - R);
         const int y = y0 + ly;
-        hy_row[j] = ly + R;
-        hy_y[j] = y;
-        hyo[j] = (int64_t)y * sy + x;
-        hy_ok[j] = (hr < 2 * R) && (x < nx + R) && (y < ny + R);
+        hrow[j] = ly + R;
+        ho[j] = (int64_t)y * sy + x;
+        hld[j] = hr < 2 * R && x < nx + R && y < ny + R;
+        hin[j] = hld[j] && x < nx && y >= 0 && y < ny;
     }
-    const int hxi = threadIdx.x;
-    const bool hx_any = hxi < 2 * R * TY;
-    int hx_lx = 0, hx_ly = 0, hx_x = 0, hx_y = 0;
+    const bool hx_any = threadIdx.x < 2 * R * TY;
+    int hx_lx = 0, hx_ly = 0;
     int64_t hxo = 0;
-    bool hx_ok = false;
+    bool hx_in = false, hx_ld = false;
     if (hx_any) {
-        const int col = hxi % (2 * R), row = hxi / (2 * R);
-        hx_x = col < R ? x0 - R + col : x0 + 64 + (col - R);
-        hx_y = y0 + row;
-        hx_lx = (col < R ? col : 64 + R + (col - R));
+        const int col = threadIdx.x % (2 * R), row = threadIdx.x / (2 * R);
+        const int xx = col < R ? x0 - R + col : x0 + 64 + (col - R);
+        const int yy = y0 + row;
+        hx_lx = col < R ? col : 64 + R + (col - R);
         hx_ly = row + R;
-        hxo = (int64_t)hx_y * sy + hx_x;
-        hx_ok = (hx_x < nx + R) && (hx_y < ny + R);
+        hxo = (int64_t)yy * sy + xx;
+        hx_ld = xx < nx + R && yy < ny + R;
+        hx_in = hx_ld && xx >= 0 && xx < nx && yy < ny;
     }
 
-    float qv[RPT][Q], qu[RPT][Q];
+    // v = c * lambda_{m+1} on the interior, 0 elsewhere
+    auto vload = [&](int64_t o, bool in) -> float {
+        const int64_t a = in ? o : 0;
+        const float l = L1[a];
+        const float c = load_coef(C, a);
+        return in ? c * l : 0.0f;
+    };
+    auto uload = [&](int f, int64_t o, bool ok) -> float {
+        const float v = U[f][ok ? o : 0];
+        return ok ? v : 0.0f;
+    };
+    auto zok = [&](int z) { return z >= 0 && z < nz; };
+
+    // register queues: qv[i][k] = v at plane z - R + k; qr = lambda_{m+1} at z .. z + R
+    float qv[RPT][Q], qr[RPT][R + 1], qu[NUA][RPT][Q];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
+        qv[i][0] = qr[i][0] = 0.0f;
+#pragma unroll
+        for (int f = 0; f < NUA; ++f) qu[f][i][0] = 0.0f;
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int zz = z0 - R - 1 + k;
-            const int64_t zo = (int64_t)zz * sz;
-            qv[i][k] = ld_ok[i] ? vload(zo, colo[i], x, ys[i], zz) : 0.0f;
-            qu[i][k] = ld_ok[i] ? U[zo + colo[i]] : 0.0f;
+            const int64_t o = (int64_t)zz * sz + co[i];
+            qv[i][k] = vload(o, cin[i] && zok(zz));
+            if (k >= R) qr[i][k - R] = L1[cin[i] && zok(zz) ? o : 0];
+#pragma unroll
+            for (int f = 0; f < NU; ++f) qu[f][i][k] = uload(f, o, cld[i]);
         }
-        qv[i][0] = qu[i][0] = 0.0f;
     }
+    // operands of plane z (prefetched one plane ahead)
+    float nv[RPT], nr[RPT], nu[NUA][RPT], l2n[RPT];
+    double gn[RPT];
+    float hv[HYJ], hu[NUA][HYJ], xv = 0.0f, xu[NUA];
+    auto fetch = [&](int z) {
+        const int64_t zh = (int64_t)(z + R) * sz, zo = (int64_t)z * sz;
+        const bool hin_z = zok(z + R), in_z = zok(z);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            nv[i] = vload(zh + co[i], cin[i] && hin_z);
+            nr[i] = L1[cin[i] && hin_z ? zh + co[i] : 0];
+#pragma unroll
+            for (int f = 0; f < NU; ++f) nu[f][i] = uload(f, zh + co[i], cld[i]);
+            l2n[i] = L2[cst[i] ? zo + co[i] : 0];
+            if constexpr (NU > 0) gn[i] = G[cst[i] ? zo + co[i] : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < HYJ; ++j) {
+            hv[j] = vload(zo + ho[j], hin[j] && in_z);
+#pragma unroll
+            for (int f = 0; f < NU; ++f) hu[f][j] = uload(f, zo + ho[j], hld[j]);
+        }
+        xv = vload(zo + hxo, hx_in && in_z);
+#pragma unroll
+        for (int f = 0; f < NU; ++f) xu[f] = uload(f, zo + hxo, hx_ld);
+    };
+    fetch(z0);
 
     for (int z = z0; z < z1; ++z) {
         const int b = (z - z0) & 1;
         const int64_t zo = (int64_t)z * sz;
-        const int zn = z + R;
-        const int64_t zno = (int64_t)zn * sz;
+        float l2c[RPT];
+        double gc[RPT];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
 #pragma unroll
-            for (int k = 0; k < Q - 1; ++k) {
-                qv[i][k] = qv[i][k + 1];
-                qu[i][k] = qu[i][k + 1];
+            for (int k = 0; k < Q - 1; ++k) qv[i][k] = qv[i][k + 1];
+            qv[i][Q - 1] = nv[i];
+#pragma unroll
+            for (int k = 0; k < R; ++k) qr[i][k] = qr[i][k + 1];
+            qr[i][R] = nr[i];
+#pragma unroll
+            for (int f = 0; f < NU; ++f) {
+#pragma unroll
+                for (int k = 0; k < Q - 1; ++k) qu[f][i][k] = qu[f][i][k + 1];
+                qu[f][i][Q - 1] = nu[f][i];
             }
-            qv[i][Q - 1] = ld_ok[i] ? vload(zno, colo[i], x, ys[i], zn) : 0.0f;
-            qu[i][Q - 1] = ld_ok[i] ? U[zno + colo[i]] : 0.0f;
-            ldv[b][R + wv + NW * i][R + lane] = qv[i][R];
-            ldu[b][R + wv + NW * i][R + lane] = qu[i][R];
+            l2c[i] = l2n[i];
+            gc[i] = NU > 0 ? gn[i] : 0.0;
+            lds[0][b][R + wv + NW * i][R + lane] = qv[i][R];
+#pragma unroll
+            for (int f = 0; f < NU; ++f) lds[1 + f][b][R + wv + NW * i][R + lane] = qu[f][i][R];
         }
 #pragma unroll
         for (int j = 0; j < HYJ; ++j)
             if (wv + NW * j < 2 * R) {
-                ldv[b][hy_row[j]][R + lane] = hy_ok[j] ? vload(zo, hyo[j], x, hy_y[j], z) : 0.0f;
-                ldu[b][hy_row[j]][R + lane] = hy_ok[j] ? U[zo + hyo[j]] : 0.0f;
+                lds[0][b][hrow[j]][R + lane] = hv[j];
+#pragma unroll
+                for (int f = 0; f < NU; ++f) lds[1 + f][b][hrow[j]][R + lane] = hu[f][j];
             }
         if (hx_any) {
-            ldv[b][hx_ly][hx_lx] = hx_ok ? vload(zo, hxo, hx_x, hx_y, z) : 0.0f;
-            ldu[b][hx_ly][hx_lx] = hx_ok ? U[zo + hxo] : 0.0f;
-        }
-        float l1c[RPT], l2c[RPT];
+            lds[0][b][hx_ly][hx_lx] = xv;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            l1c[i] = st_ok[i] ? L1[zo + colo[i]] : 0.0f;
-            l2c[i] = st_ok[i] ? L2[zo + colo[i]] : 0.0f;
+            for (int f = 0; f < NU; ++f) lds[1 + f][b][hx_ly][hx_lx] = xu[f];
         }
+        if (z + 1 < z1) fetch(z + 1);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             const int ly = R + wv + NW * i, lx = R + lane;
-            nbhd<R> nv;
-            nv.c = qv[i][R];
-            double lu = wd.w[0] * (double)qu[i][R];
+            nbhd<R> n;
+            n.c = qv[i][R];
 #pragma unroll
             for (int r = 1; r <= R; ++r) {
-                nv.pair[0][r - 1] = ldv[b][ly][lx - r] + ldv[b][ly][lx + r];
-                nv.pair[1][r - 1] = ldv[b][ly - r][lx] + ldv[b][ly + r][lx];
-                nv.pair[2][r - 1] = qv[i][R - r] + qv[i][R + r];
-                const double px = (double)ldu[b][ly][lx - r] + (double)ldu[b][ly][lx + r];
-                const double py = (double)ldu[b][ly - r][lx] + (double)ldu[b][ly + r][lx];
-                const double pz = (double)qu[i][R - r] + (double)qu[i][R + r];
-                lu = __builtin_fma(wd.w[r], (px + py) + pz, lu);
+                n.pair[0][r - 1] = lds[0][b][ly][lx - r] + lds[0][b][ly][lx + r];
+                n.pair[1][r - 1] = lds[0][b][ly - r][lx] + lds[0][b][ly + r][lx];
+                n.pair[2][r - 1] = qv[i][R - r] + qv[i][R + r];
             }
-            const float lv = op_lap8(wt, nv);
-            const float lam_n = op_leapfrog(1.0f, lv, l1c[i], l2c[i]);
-            if (st_ok[i]) {
-                L2[zo + colo[i]] = lam_n;
-                G[zo + colo[i]] += (double)l1c[i] * lu;
+            const float lam1c = qr[i][0];
+            const float lam_m = op_leapfrog(1.0f, op_lap8(wt, n), lam1c, l2c[i]);
+            if constexpr (NU > 0) {
+                // multipliers of the u fields, in the order they were bound
+                float mul[NUA];
+                {
+                    int f = 0;
+                    if constexpr ((TERMS & 1) != 0) mul[f++] = l2c[i];
+                    if constexpr ((TERMS & 2) != 0) mul[f++] = lam1c;
+                    if constexpr ((TERMS & 4) != 0) mul[f++] = lam_m;
+                }
+                double sum = 0.0;
+#pragma unroll
+                for (int f = 0; f < NU; ++f) {
+                    double lu = wd.w[0] * (double)qu[f][i][R];
+#pragma unroll
+                    for (int r = 1; r <= R; ++r) {
+                        const double px =
+                            (double)lds[1 + f][b][ly][lx - r] + (double)lds[1 + f][b][ly][lx + r];
+                        const double py =
+                            (double)lds[1 + f][b][ly - r][lx] + (double)lds[1 + f][b][ly + r][lx];
+                        const double pz = (double)qu[f][i][R - r] + (double)qu[f][i][R + r];
+                        lu = __builtin_fma(wd.w[r], (px + py) + pz, lu);
+                    }
+                    sum = f == 0 ? (double)mul[f] * lu : __builtin_fma((double)mul[f], lu, sum);
+                }
+                if (cst[i]) G[zo + co[i]] = gc[i] + sum;
             }
+            if (cst[i]) L2[zo + co[i]] = lam_m;
         }
     }
 }
@@ -212,16 +296,18 @@ int util_blocks(const dims& d) {
     return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
 }
 
-constexpr int ADJ_RPT = 4;
-
 }  // namespace
 
-hipError_t launch_adjoint_step(bool bf16, const float* lam1, float* lam2, const void* coef,
-                               const float* us, double* g, const dims& d, const double* w,
-                               int zchunk, hipStream_t s) {
-    constexpr int TY = NW * ADJ_RPT;
+namespace {
+
+template <typename CT, int RPT, int TERMS>
+hipError_t launch_terms(const float* lam1, float* lam2, const CT* coef, const float* up,
+                        const float* uc, const float* un, double* g, const dims& d,
+                        const weights& wt, const w64& wd, int zchunk, hipStream_t s) {
+    constexpr int TY = NW * RPT;
     const int gx = (d.nx + 63) / 64, gy = (d.ny + TY - 1) / TY;
     if (zchunk <= 0) {
+        // about 2048 workgroups, chunks of at least 4R planes
         const long long txy = (long long)gx * gy;
         long long nzc = (2048 + txy - 1) / txy;
         zchunk = (int)((d.nz + nzc - 1) / nzc);
@@ -231,6 +317,39 @@ hipError_t launch_adjoint_step(bool bf16, const float* lam1, float* lam2, const 
     const int gz = (d.nz + zchunk - 1) / zchunk;
     const long long ntiles = (long long)gx * gy * gz;
     if (ntiles <= 0) return hipSuccess;
+    if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((adjoint_step_kernel<CT, RPT, TERMS>), dim3((unsigned)ntiles), dim3(NT), 0,
+                       s, lam1, lam2, coef, up, uc, un, g, d.nx, d.ny, d.nz, d.sy, d.sz, d.org(),
+                       wt, wd, zchunk, gx, gy, (int)ntiles);
+    return hipGetLastError();
+}
+
+template <typename CT>
+hipError_t launch_ct(const float* lam1, float* lam2, const CT* coef, const float* up,
+                     const float* uc, const float* un, double* g, const dims& d, const weights& wt,
+                     const w64& wd, int zchunk, hipStream_t s) {
+    const int terms = (up ? 1 : 0) | (uc ? 2 : 0) | (un ? 4 : 0);
+#define STN_ADJ_CASE(T, RPT) \
+    case T: return launch_terms<CT, RPT, T>(lam1, lam2, coef, up, uc, un, g, d, wt, wd, zchunk, s)
+    switch (terms) {
+        STN_ADJ_CASE(0, 4);
+        STN_ADJ_CASE(1, 2);
+        STN_ADJ_CASE(2, 2);
+        STN_ADJ_CASE(3, 2);
+        STN_ADJ_CASE(4, 2);
+        STN_ADJ_CASE(6, 2);
+        STN_ADJ_CASE(7, 2);
+    default: return hipErrorInvalidValue;
+    }
+#undef STN_ADJ_CASE
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_step(bool bf16, const float* lam1, float* lam2, const void* coef,
+                               const float* u_p, const float* u_c, const float* u_n, double* g,
+                               const dims& d, const double* w, int zchunk, hipStream_t s) {
+    if ((u_p || u_c || u_n) && !g) return hipErrorInvalidValue;
     weights wt;
     w64 wd;
     for (int i = 0; i < 5; ++i) {
@@ -239,14 +358,10 @@ hipError_t launch_adjoint_step(bool bf16, const float* lam1, float* lam2, const 
     }
     wt.alpha = 1.0f;
     if (bf16)
-        hipLaunchKernelGGL((adjoint_step_kernel<uint16_t, ADJ_RPT>), dim3((unsigned)ntiles), dim3(NT),
-                           0, s, lam1, lam2, static_cast<const uint16_t*>(coef), us, g, d.nx, d.ny,
-                           d.nz, d.sy, d.sz, d.org(), wt, wd, zchunk, gx, gy, (int)ntiles);
-    else
-        hipLaunchKernelGGL((adjoint_step_kernel<float, ADJ_RPT>), dim3((unsigned)ntiles), dim3(NT), 0,
-                           s, lam1, lam2, static_cast<const float*>(coef), us, g, d.nx, d.ny, d.nz,
-                           d.sy, d.sz, d.org(), wt, wd, zchunk, gx, gy, (int)ntiles);
-    return hipGetLastError();
+        return launch_ct(lam1, lam2, static_cast<const uint16_t*>(coef), u_p, u_c, u_n, g, d, wt,
+                         wd, zchunk, s);
+    return launch_ct(lam1, lam2, static_cast<const float*>(coef), u_p, u_c, u_n, g, d, wt, wd,
+                     zchunk, s);
 }
 
 hipError_t launch_scale_copy(float* dst, const float* src, float a, const dims& d, hipStream_t s) {

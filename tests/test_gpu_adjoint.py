@@ -5,7 +5,9 @@
   tiles with ragged tails;
 * the checkpoint interval only changes the schedule: every interval, with or
   without a forward recording, naive or blocked forward, gives bit-identical
-  gradients (the recomputation reproduces the forward bit for bit);
+  gradients for u_{-1} and u_0 (the recomputation reproduces the forward bit
+  for bit) and FP64 coefficient gradients that differ only in the grouping of
+  their additions;
 * the torch.autograd binding returns the same gradients;
 * nt = 0 and nt = 1 edge cases.
 """
@@ -89,8 +91,12 @@ def test_adjoint_schedule_is_bitwise_invariant():
     for kw in (dict(k=1), dict(k=7), dict(k=15), dict(k=4, record=False),
                dict(k=5, scheme=st.BLOCKED), dict(k=3, scheme=st.BLOCKED, record=False)):
         got = grads_gpu(wl, nt, **kw)
-        for a, b, name in zip(got[:3], ref[:3], ("um1", "u0", "c")):
+        for a, b, name in zip(got[:2], ref[:2], ("um1", "u0")):
             assert np.array_equal(a, b), (kw, name)
+        # the FP64 gradient sums the same FP32-exact terms; only the grouping
+        # of the additions follows the checkpoint segments
+        diff = np.abs(got[2] - ref[2]).max() / np.abs(ref[2]).max()
+        assert diff <= 1e-13, (kw, diff)
 
 
 def test_adjoint_nt_zero_and_one():
