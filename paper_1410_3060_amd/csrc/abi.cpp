@@ -424,38 +424,67 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
         if (e != hipSuccess) return dev_fail(e, "adjoint forward");
     }
     const int k = rec.every;
-    // workspace: k + 1 segment slots and two lambda fields
+    // workspace: segment slots for levels a+1 .. a+k-1 (levels a-1 and a are
+    // read from the checkpoint itself), two adjoint fields and a flag
     void* p = nullptr;
-    rc = ws_alloc(ctx, (size_t)(k + 3) * span * sizeof(float), &p);
+    const size_t nslot = (size_t)(k > 1 ? k - 1 : 0);
+    rc = ws_alloc(ctx, (nslot + 2) * span * sizeof(float) + 256, &p);
     if (rc) return rc;
-    float* slots = static_cast<float*>(p);
-    float* lam_a = slots + (size_t)(k + 1) * span;
+    float* ws = static_cast<float*>(p);
+    float* lam_a = ws + nslot * span;
     float* lam_b = lam_a + span;
-    auto slot = [&](int i) { return slots + (size_t)i * span; };
+    int* flag = reinterpret_cast<int*>(lam_b + span);
+    const float* seg0 = nullptr;  // checkpoint of the current segment: u_{a-1}, u_a
+    const float* seg1 = nullptr;
+    auto slot = [&](int i) -> float* {
+        if (i == 0) return const_cast<float*>(seg0);
+        if (i == 1) return const_cast<float*>(seg1);
+        return ws + (size_t)(i - 2) * span;
+    };
+    auto done = [&](hipError_t err, const char* what) {
+        const hipError_t es = hipStreamSynchronize(st);
+        ws_free(ctx, p);
+        if (err == hipSuccess) err = es;
+        return err == hipSuccess ? STENCIL_OK : dev_fail(err, what);
+    };
+    // Scaled form (mu = c lambda) unless some coefficient is zero, tiny or
+    // not finite there.
+    int bad = 0;
+    e = stn::launch_coef_check(flag, bf16, c->arrays, d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return done(e, "adjoint coefficient check");
+    const bool mu = bad == 0;
     // the boundary shell is taken as time independent: every slot gets the
     // shell of the buffer holding level 0 (its interior is overwritten)
-    e = hipSuccess;
-    for (int i = 0; i <= k && e == hipSuccess; ++i)
-        e = hipMemcpyAsync(slot(i), g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+    for (size_t i = 0; i < nslot && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(ws + i * span, g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = stn::launch_zero_span(lam_a, 2 * span, st);
-    if (e == hipSuccess) e = stn::launch_scale_copy(lam_a, seed, 1.0f, d, st);
+    if (e == hipSuccess)
+        e = mu ? stn::launch_mul_coef(lam_a, seed, bf16, c->arrays, d, st)
+               : stn::launch_scale_copy(lam_a, seed, 1.0f, d, st);
     if (e == hipSuccess) e = stn::launch_zero_f64(g_c, d, st);
-    if (e != hipSuccess) {
-        ws_free(ctx, p);
-        return dev_fail(e, "adjoint setup");
-    }
-    float* cur = lam_a;  // lambda_{s+1}
-    float* nxt = lam_b;  // lambda_{s+2}, becomes lambda_s
+    if (e != hipSuccess) return done(e, "adjoint setup");
+    float* cur = lam_a;  // lambda_{m+1} (or mu_{m+1})
+    float* nxt = lam_b;  // lambda_{m+2}, becomes lambda_m
     const stn::host_weights wt = to_weights(c);
     const double* w = c->w;
+    // one reverse step m; up/uc/un: u_{m+1}, u_m, u_{m-1} for its gradient terms
+    auto step = [&](const float* up, const float* uc, const float* un) {
+        hipError_t r;
+        if (mu && !up && !uc && !un)
+            r = stn::launch_naive_step(5, bf16, cur, nxt, nxt, c->arrays, c->sk, d, wt, 0, st);
+        else
+            r = stn::launch_adjoint_step(bf16, mu, cur, nxt, c->arrays, up, uc, un, g_c, d, w, 0,
+                                         st);
+        std::swap(cur, nxt);
+        return r;
+    };
     for (int q = rec.n - 1; q >= 0 && e == hipSuccess; --q) {
         const int64_t a = (int64_t)q * k;
         const int64_t b = std::min<int64_t>(a + k, nt);
-        e = hipMemcpyAsync(slot(0), rec.buf + (2 * (size_t)q) * span, span * sizeof(float),
-                           hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(slot(1), rec.buf + (2 * (size_t)q + 1) * span, span * sizeof(float),
-                               hipMemcpyDeviceToDevice, st);
+        seg0 = rec.buf + (2 * (size_t)q) * span;
+        seg1 = seg0 + span;
         // slot i holds u_{a-1+i}
         for (int64_t i = 1; i + a < b && e == hipSuccess; ++i)
             e = stn::launch_naive_step(5, bf16, slot((int)i), slot((int)i - 1), slot((int)i + 1),
@@ -464,12 +493,6 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
         // group also adds the gradient terms of its two neighbours, so the
         // FP64 gradient is read and written once per group
         auto U = [&](int64_t n) -> const float* { return slot((int)(n - a + 1)); };
-        auto step = [&](const float* up, const float* uc, const float* un) {
-            hipError_t r = stn::launch_adjoint_step(bf16, cur, nxt, c->arrays, up, uc, un, g_c, d,
-                                                    w, 0, st);
-            std::swap(cur, nxt);
-            return r;
-        };
         for (int64_t s = b - 1; s >= a && e == hipSuccess;) {
             const int64_t left = s - a + 1;
             if (left >= 3) {
@@ -487,16 +510,15 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
             }
         }
     }
-    if (e == hipSuccess) e = stn::launch_scale_copy(g_u0, cur, 1.0f, d, st);
-    if (e == hipSuccess) e = stn::launch_scale_copy(g_um1, nxt, -1.0f, d, st);
-    if (e != hipSuccess) {
-        (void)hipStreamSynchronize(st);
-        ws_free(ctx, p);
-        return dev_fail(e, "adjoint");
+    if (e == hipSuccess) {
+        if (mu) {
+            e = stn::launch_finish_mu(g_c, g_u0, g_um1, cur, nxt, bf16, c->arrays, d, st);
+        } else {
+            e = stn::launch_scale_copy(g_u0, cur, 1.0f, d, st);
+            if (e == hipSuccess) e = stn::launch_scale_copy(g_um1, nxt, -1.0f, d, st);
+        }
     }
-    e = hipStreamSynchronize(st);
-    ws_free(ctx, p);
-    return e == hipSuccess ? STENCIL_OK : dev_fail(e, "adjoint");
+    return done(e, "adjoint");
 }
 
 }  // namespace

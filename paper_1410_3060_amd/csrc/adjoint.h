@@ -14,9 +14,23 @@ namespace stn {
 // and, in FP64, g += lambda_{m+2} L8(u_p) + lambda_{m+1} L8(u_c) + lambda_m L8(u_n)
 // for the u fields given (u_p = u_{m+1}, u_c = u_m, u_n = u_{m-1}; null
 // pointers drop their term, all null leaves g untouched).  w: the five L8 weights.
-hipError_t launch_adjoint_step(bool coef_bf16, const float* lam1, float* lam2, const void* coef,
-                               const float* u_p, const float* u_c, const float* u_n, double* g,
-                               const dims& d, const double* w, int zchunk, hipStream_t s);
+// mu: the fields hold mu = c * lambda instead (zero boundary shells), the step
+// is mu_m = 2 mu_{m+1} - mu_{m+2} + c L8(mu_{m+1}) and the terms use mu.
+hipError_t launch_adjoint_step(bool coef_bf16, bool mu, const float* lam1, float* lam2,
+                               const void* coef, const float* u_p, const float* u_c,
+                               const float* u_n, double* g, const dims& d, const double* w,
+                               int zchunk, hipStream_t s);
+
+// Scaled form helpers (interior only): dst = c * src; the final division
+// g /= c, g_u0 = mu0 / c, g_um1 = -mu1 / c; and flag = 1 if some |c| is below
+// 2^-60 or not finite (flag is cleared first).
+hipError_t launch_mul_coef(float* dst, const float* src, bool coef_bf16, const void* coef,
+                           const dims& d, hipStream_t s);
+hipError_t launch_finish_mu(double* g, float* g_u0, float* g_um1, const float* mu0,
+                            const float* mu1, bool coef_bf16, const void* coef, const dims& d,
+                            hipStream_t s);
+hipError_t launch_coef_check(int* flag, bool coef_bf16, const void* coef, const dims& d,
+                             hipStream_t s);
 
 // Interior-only helpers (the boundary shell of dst is never written).
 hipError_t launch_scale_copy(float* dst, const float* src, float a, const dims& d, hipStream_t s);

@@ -23,6 +23,13 @@
 // (TERMS selects which are present).  Each L8(u) is evaluated in FP64 from the
 // FP32 values, so that the cancellation inside the stencil sum does not cost
 // FP32 digits in the coefficient gradient.
+//
+// Scaled form (MU).  Where c has no zero, mu = c * lambda obeys
+//     mu_m = 2 mu_{m+1} - mu_{m+2} + c L8(mu_{m+1}),
+// the forward leapfrog itself, so a step needs no product at every stencil
+// load and a step without gradient terms is the forward kernel.  The
+// gradient is then accumulated as sum mu_{n+1} L8(u_n) and divided by c once
+// at the end, as are lambda_0 = mu_0 / c and lambda_1 = mu_1 / c.
 #include "adjoint.h"
 #include "common.h"
 #include "point_ops.h"
@@ -31,8 +38,6 @@ namespace stn {
 
 namespace {
 
-constexpr int NT = 256;
-constexpr int NW = 4;
 constexpr int R = 4;
 constexpr int Q = 2 * R + 1;
 
@@ -41,8 +46,8 @@ struct w64 {
 };
 
 // TERMS: bit 0 the term of step m+1, bit 1 of step m, bit 2 of step m-1.
-template <typename CT, int RPT, int TERMS>
-__global__ __launch_bounds__(NT) void adjoint_step_kernel(
+template <typename CT, int NW, int RPT, int TERMS, bool MU>
+__global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
     const float* __restrict__ lam1, float* lam2, const CT* __restrict__ coef,
     const float* u_p, const float* u_c, const float* u_n, double* __restrict__ g, int nx, int ny,
     int nz, int64_t sy, int64_t sz, int64_t org, weights wt, w64 wd, int zchunk, int gx, int gy,
@@ -132,6 +137,10 @@ __global__ __launch_bounds__(NT) void adjoint_step_kernel(
         const float v = U[f][ok ? o : 0];
         return ok ? v : 0.0f;
     };
+    auto uload1 = [&](const float* P, int64_t o, bool ok) -> float {
+        const float v = P[ok ? o : 0];
+        return ok ? v : 0.0f;
+    };
     auto zok = [&](int z) { return z >= 0 && z < nz; };
 
     // register queues: qv[i][k] = v at plane z - R + k; qr = lambda_{m+1} at z .. z + R
@@ -145,14 +154,22 @@ __global__ __launch_bounds__(NT) void adjoint_step_kernel(
         for (int k = 1; k < Q; ++k) {
             const int zz = z0 - R - 1 + k;
             const int64_t o = (int64_t)zz * sz + co[i];
-            qv[i][k] = vload(o, cin[i] && zok(zz));
-            if (k >= R) qr[i][k - R] = L1[cin[i] && zok(zz) ? o : 0];
+            if constexpr (MU) {
+                qv[i][k] = uload1(L1, o, cld[i]);
+            } else {
+                const bool in = cin[i] && zok(zz);
+                const int64_t a = in ? o : 0;
+                const float l = L1[a];
+                const float c = load_coef(C, a);
+                qv[i][k] = in ? c * l : 0.0f;
+                if (k >= R) qr[i][k - R] = l;
+            }
 #pragma unroll
             for (int f = 0; f < NU; ++f) qu[f][i][k] = uload(f, o, cld[i]);
         }
     }
     // operands of plane z (prefetched one plane ahead)
-    float nv[RPT], nr[RPT], nu[NUA][RPT], l2n[RPT];
+    float nv[RPT], nr[RPT], ncp[RPT], nu[NUA][RPT], l2n[RPT];
     double gn[RPT];
     float hv[HYJ], hu[NUA][HYJ], xv = 0.0f, xu[NUA];
     auto fetch = [&](int z) {
@@ -160,8 +177,20 @@ __global__ __launch_bounds__(NT) void adjoint_step_kernel(
         const bool hin_z = zok(z + R), in_z = zok(z);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            nv[i] = vload(zh + co[i], cin[i] && hin_z);
-            nr[i] = L1[cin[i] && hin_z ? zh + co[i] : 0];
+            if constexpr (MU) {
+                // mu fields carry a zero boundary shell
+                const float l = L1[cld[i] ? zh + co[i] : 0];
+                nv[i] = cld[i] ? l : 0.0f;
+                nr[i] = 0.0f;
+                ncp[i] = load_coef(C, cst[i] ? zo + co[i] : 0);
+            } else {
+                const bool in = cin[i] && hin_z;
+                const int64_t a = in ? zh + co[i] : 0;
+                const float l = L1[a];
+                const float c = load_coef(C, a);
+                nr[i] = l;
+                nv[i] = in ? c * l : 0.0f;
+            }
 #pragma unroll
             for (int f = 0; f < NU; ++f) nu[f][i] = uload(f, zh + co[i], cld[i]);
             l2n[i] = L2[cst[i] ? zo + co[i] : 0];
@@ -169,11 +198,17 @@ __global__ __launch_bounds__(NT) void adjoint_step_kernel(
         }
 #pragma unroll
         for (int j = 0; j < HYJ; ++j) {
-            hv[j] = vload(zo + ho[j], hin[j] && in_z);
+            if constexpr (MU)
+                hv[j] = uload1(L1, zo + ho[j], hld[j]);
+            else
+                hv[j] = vload(zo + ho[j], hin[j] && in_z);
 #pragma unroll
             for (int f = 0; f < NU; ++f) hu[f][j] = uload(f, zo + ho[j], hld[j]);
         }
-        xv = vload(zo + hxo, hx_in && in_z);
+        if constexpr (MU)
+            xv = uload1(L1, zo + hxo, hx_ld);
+        else
+            xv = vload(zo + hxo, hx_in && in_z);
 #pragma unroll
         for (int f = 0; f < NU; ++f) xu[f] = uload(f, zo + hxo, hx_ld);
     };
@@ -182,7 +217,7 @@ __global__ __launch_bounds__(NT) void adjoint_step_kernel(
     for (int z = z0; z < z1; ++z) {
         const int b = (z - z0) & 1;
         const int64_t zo = (int64_t)z * sz;
-        float l2c[RPT];
+        float l2c[RPT], cpt[RPT];
         double gc[RPT];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
@@ -199,6 +234,7 @@ __global__ __launch_bounds__(NT) void adjoint_step_kernel(
                 qu[f][i][Q - 1] = nu[f][i];
             }
             l2c[i] = l2n[i];
+            cpt[i] = MU ? ncp[i] : 0.0f;
             gc[i] = NU > 0 ? gn[i] : 0.0;
             lds[0][b][R + wv + NW * i][R + lane] = qv[i][R];
 #pragma unroll
@@ -229,8 +265,8 @@ __global__ __launch_bounds__(NT) void adjoint_step_kernel(
                 n.pair[1][r - 1] = lds[0][b][ly - r][lx] + lds[0][b][ly + r][lx];
                 n.pair[2][r - 1] = qv[i][R - r] + qv[i][R + r];
             }
-            const float lam1c = qr[i][0];
-            const float lam_m = op_leapfrog(1.0f, op_lap8(wt, n), lam1c, l2c[i]);
+            const float lam1c = MU ? qv[i][R] : qr[i][0];
+            const float lam_m = op_leapfrog(MU ? cpt[i] : 1.0f, op_lap8(wt, n), lam1c, l2c[i]);
             if constexpr (NU > 0) {
                 // multipliers of the u fields, in the order they were bound
                 float mul[NUA];
@@ -284,6 +320,55 @@ __global__ void zero_kernel(T* dst, int nx, int ny, int nz, int64_t sy, int64_t 
     }
 }
 
+// Scaled form: dst = c * src on the interior.
+template <typename CT>
+__global__ void mul_coef_kernel(float* dst, const float* src, const CT* coef, int nx, int ny,
+                                int nz, int64_t sy, int64_t sz, int64_t org) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = i % nx, y = (i / nx) % ny, z = i / ((int64_t)nx * ny);
+        const int64_t o = org + z * sz + y * sy + x;
+        dst[o] = load_coef(coef, o) * src[o];
+    }
+}
+
+// Scaled form, last pass: g /= c, g_u0 = mu_0 / c, g_um1 = -mu_1 / c.
+template <typename CT>
+__global__ void finish_mu_kernel(double* g, float* g_u0, float* g_um1, const float* mu0,
+                                 const float* mu1, const CT* coef, int nx, int ny, int nz,
+                                 int64_t sy, int64_t sz, int64_t org) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = i % nx, y = (i / nx) % ny, z = i / ((int64_t)nx * ny);
+        const int64_t o = org + z * sz + y * sy + x;
+        const float c = load_coef(coef, o);
+        g[o] = g[o] / (double)c;
+        g_u0[o] = mu0[o] / c;
+        g_um1[o] = -(mu1[o] / c);
+    }
+}
+
+// flag <- 1 if some interior coefficient is zero, tiny (|c| < 2^-60) or not
+// finite: the scaled form cannot be divided back there.  Only 1 is ever
+// written, so the order of the stores does not matter.
+template <typename CT>
+__global__ void coef_check_kernel(int* flag, const CT* coef, int nx, int ny, int nz, int64_t sy,
+                                  int64_t sz, int64_t org) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = i % nx, y = (i / nx) % ny, z = i / ((int64_t)nx * ny);
+        const float c = fabsf(load_coef(coef, org + z * sz + y * sy + x));
+        bad |= !(c >= 0x1p-60f && c <= 3.0e38f);
+    }
+    if (bad) *flag = 1;
+}
+
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
+
 __global__ void zero_span_kernel(float* dst, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
@@ -300,7 +385,7 @@ int util_blocks(const dims& d) {
 
 namespace {
 
-template <typename CT, int RPT, int TERMS>
+template <typename CT, int NW, int RPT, int TERMS, bool MU>
 hipError_t launch_terms(const float* lam1, float* lam2, const CT* coef, const float* up,
                         const float* uc, const float* un, double* g, const dims& d,
                         const weights& wt, const w64& wd, int zchunk, hipStream_t s) {
@@ -318,27 +403,32 @@ hipError_t launch_terms(const float* lam1, float* lam2, const CT* coef, const fl
     const long long ntiles = (long long)gx * gy * gz;
     if (ntiles <= 0) return hipSuccess;
     if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((adjoint_step_kernel<CT, RPT, TERMS>), dim3((unsigned)ntiles), dim3(NT), 0,
+    hipLaunchKernelGGL((adjoint_step_kernel<CT, NW, RPT, TERMS, MU>), dim3((unsigned)ntiles),
+                       dim3(NW * 64), 0,
                        s, lam1, lam2, coef, up, uc, un, g, d.nx, d.ny, d.nz, d.sy, d.sz, d.org(),
                        wt, wd, zchunk, gx, gy, (int)ntiles);
     return hipGetLastError();
 }
 
-template <typename CT>
+template <typename CT, bool MU>
 hipError_t launch_ct(const float* lam1, float* lam2, const CT* coef, const float* up,
                      const float* uc, const float* un, double* g, const dims& d, const weights& wt,
                      const w64& wd, int zchunk, hipStream_t s) {
     const int terms = (up ? 1 : 0) | (uc ? 2 : 0) | (un ? 4 : 0);
-#define STN_ADJ_CASE(T, RPT) \
-    case T: return launch_terms<CT, RPT, T>(lam1, lam2, coef, up, uc, un, g, d, wt, wd, zchunk, s)
+#define STN_ADJ_CASE(T, NW, RPT)                                                           \
+    case T:                                                                                \
+        return launch_terms<CT, NW, RPT, T, MU>(lam1, lam2, coef, up, uc, un, g, d, wt, wd, \
+                                                zchunk, s)
+    // waves per workgroup and rows per lane by term count (registers: one
+    // 2R+1 queue per stencil field and row)
     switch (terms) {
-        STN_ADJ_CASE(0, 4);
-        STN_ADJ_CASE(1, 2);
-        STN_ADJ_CASE(2, 2);
-        STN_ADJ_CASE(3, 2);
-        STN_ADJ_CASE(4, 2);
-        STN_ADJ_CASE(6, 2);
-        STN_ADJ_CASE(7, 2);
+        STN_ADJ_CASE(0, 4, 4);
+        STN_ADJ_CASE(1, 4, 2);
+        STN_ADJ_CASE(2, 4, 2);
+        STN_ADJ_CASE(3, 4, 2);
+        STN_ADJ_CASE(4, 4, 2);
+        STN_ADJ_CASE(6, 4, 2);
+        STN_ADJ_CASE(7, 4, 2);
     default: return hipErrorInvalidValue;
     }
 #undef STN_ADJ_CASE
@@ -346,9 +436,10 @@ hipError_t launch_ct(const float* lam1, float* lam2, const CT* coef, const float
 
 }  // namespace
 
-hipError_t launch_adjoint_step(bool bf16, const float* lam1, float* lam2, const void* coef,
-                               const float* u_p, const float* u_c, const float* u_n, double* g,
-                               const dims& d, const double* w, int zchunk, hipStream_t s) {
+hipError_t launch_adjoint_step(bool bf16, bool mu, const float* lam1, float* lam2,
+                               const void* coef, const float* u_p, const float* u_c,
+                               const float* u_n, double* g, const dims& d, const double* w,
+                               int zchunk, hipStream_t s) {
     if ((u_p || u_c || u_n) && !g) return hipErrorInvalidValue;
     weights wt;
     w64 wd;
@@ -357,11 +448,13 @@ hipError_t launch_adjoint_step(bool bf16, const float* lam1, float* lam2, const 
         wd.w[i] = w[i];
     }
     wt.alpha = 1.0f;
-    if (bf16)
-        return launch_ct(lam1, lam2, static_cast<const uint16_t*>(coef), u_p, u_c, u_n, g, d, wt,
-                         wd, zchunk, s);
-    return launch_ct(lam1, lam2, static_cast<const float*>(coef), u_p, u_c, u_n, g, d, wt, wd,
-                     zchunk, s);
+    const auto* c16 = static_cast<const uint16_t*>(coef);
+    const auto* c32 = static_cast<const float*>(coef);
+    if (mu)
+        return bf16 ? launch_ct<uint16_t, true>(lam1, lam2, c16, u_p, u_c, u_n, g, d, wt, wd, zchunk, s)
+                    : launch_ct<float, true>(lam1, lam2, c32, u_p, u_c, u_n, g, d, wt, wd, zchunk, s);
+    return bf16 ? launch_ct<uint16_t, false>(lam1, lam2, c16, u_p, u_c, u_n, g, d, wt, wd, zchunk, s)
+                : launch_ct<float, false>(lam1, lam2, c32, u_p, u_c, u_n, g, d, wt, wd, zchunk, s);
 }
 
 hipError_t launch_scale_copy(float* dst, const float* src, float a, const dims& d, hipStream_t s) {
@@ -379,6 +472,45 @@ hipError_t launch_zero_f32(float* dst, const dims& d, hipStream_t s) {
 hipError_t launch_zero_f64(double* dst, const dims& d, hipStream_t s) {
     hipLaunchKernelGGL(zero_kernel<double>, dim3(util_blocks(d)), dim3(256), 0, s, dst, d.nx, d.ny,
                        d.nz, d.sy, d.sz, d.org());
+    return hipGetLastError();
+}
+
+hipError_t launch_mul_coef(float* dst, const float* src, bool bf16, const void* coef,
+                           const dims& d, hipStream_t s) {
+    if (bf16)
+        hipLaunchKernelGGL(mul_coef_kernel<uint16_t>, dim3(util_blocks(d)), dim3(256), 0, s, dst,
+                           src, static_cast<const uint16_t*>(coef), d.nx, d.ny, d.nz, d.sy, d.sz,
+                           d.org());
+    else
+        hipLaunchKernelGGL(mul_coef_kernel<float>, dim3(util_blocks(d)), dim3(256), 0, s, dst, src,
+                           static_cast<const float*>(coef), d.nx, d.ny, d.nz, d.sy, d.sz, d.org());
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_mu(double* g, float* g_u0, float* g_um1, const float* mu0,
+                            const float* mu1, bool bf16, const void* coef, const dims& d,
+                            hipStream_t s) {
+    if (bf16)
+        hipLaunchKernelGGL(finish_mu_kernel<uint16_t>, dim3(util_blocks(d)), dim3(256), 0, s, g,
+                           g_u0, g_um1, mu0, mu1, static_cast<const uint16_t*>(coef), d.nx, d.ny,
+                           d.nz, d.sy, d.sz, d.org());
+    else
+        hipLaunchKernelGGL(finish_mu_kernel<float>, dim3(util_blocks(d)), dim3(256), 0, s, g, g_u0,
+                           g_um1, mu0, mu1, static_cast<const float*>(coef), d.nx, d.ny, d.nz,
+                           d.sy, d.sz, d.org());
+    return hipGetLastError();
+}
+
+hipError_t launch_coef_check(int* flag, bool bf16, const void* coef, const dims& d,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, flag, 0);
+    if (bf16)
+        hipLaunchKernelGGL(coef_check_kernel<uint16_t>, dim3(util_blocks(d)), dim3(256), 0, s, flag,
+                           static_cast<const uint16_t*>(coef), d.nx, d.ny, d.nz, d.sy, d.sz,
+                           d.org());
+    else
+        hipLaunchKernelGGL(coef_check_kernel<float>, dim3(util_blocks(d)), dim3(256), 0, s, flag,
+                           static_cast<const float*>(coef), d.nx, d.ny, d.nz, d.sy, d.sz, d.org());
     return hipGetLastError();
 }
 
