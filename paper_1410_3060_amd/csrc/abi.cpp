@@ -68,9 +68,13 @@ struct stencil_ctx {
         int every = 0;            // checkpoint interval k
         const void* coef = nullptr;
         int dtype = 0;
-        float* buf = nullptr;     // 2 * n fields: (u_{qk-1}, u_{qk}) for q = 0 .. n-1
-        size_t span = 0;          // elements per field
+        void* buf = nullptr;      // 2 * n fields: (u_{qk-1}, u_{qk}) for q = 0 .. n-1
+        size_t bytes = 0;         // allocated size of buf
+        size_t lead = 0, stride = 0;  // placement of the fields (elements)
         int n = 0;
+        const float* field(size_t i) const {
+            return static_cast<const float*>(buf) + lead + i * stride;
+        }
     } rec;
 };
 
@@ -109,6 +113,25 @@ void ws_free(stencil_ctx* ctx, void* p) {
 int64_t field_span(const stencil_grid* g) {
     const int64_t h = g->halo;
     return (g->nz + 2 * h - 1) * g->sz + (g->ny + 2 * h - 1) * g->sy + (g->nx + 2 * h);
+}
+
+// Placement of workspace fields.  Field i of a workspace region starts `lead`
+// elements into the region plus i strides of a multiple of 64 elements, so
+// that its rows sit on the same 256-byte boundaries as those of the caller's
+// u[0] (hipMalloc regions are 256-byte aligned); a misaligned copy would
+// split every 256-byte row access of a wave over three cache lines.
+struct field_layout {
+    size_t lead = 0, stride = 0, span = 0;  // elements
+    size_t bytes(size_t n) const { return (lead + n * stride) * sizeof(float) + 256; }
+    float* at(void* base, size_t i) const { return static_cast<float*>(base) + lead + i * stride; }
+};
+
+field_layout layout_of(const stencil_grid* g) {
+    field_layout L;
+    L.span = (size_t)field_span(g);
+    L.stride = (L.span + 63) / 64 * 64;
+    L.lead = (size_t)((reinterpret_cast<uintptr_t>(g->u[0]) / sizeof(float)) % 64);
+    return L;
 }
 
 int validate_grid(int kind, const stencil_grid* g) {
@@ -247,12 +270,12 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
                     (long long)g->sy);
     const stn::dims d = to_dims(g);
     const stn::diamond_plan plan = stn::make_plan(R, dw, g->ny, nt);
-    const size_t span = (size_t)field_span(g);
-    const size_t fbytes = span * sizeof(float);
-    int rc = ensure_frontier(ctx, 2 * fbytes);
+    const field_layout FL = layout_of(g);
+    const size_t fbytes = FL.span * sizeof(float);
+    int rc = ensure_frontier(ctx, FL.bytes(2));
     if (rc) return rc;
-    float* w0 = static_cast<float*>(ctx->frontier);
-    float* w1 = w0 + span;
+    float* w0 = FL.at(ctx->frontier, 0);
+    float* w1 = FL.at(ctx->frontier, 1);
     float* u0 = static_cast<float*>(g->u[0]);
     float* u1 = static_cast<float*>(g->u[1]);
     const bool lf = kind_leapfrog(kind);
@@ -331,20 +354,24 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
 // the boundary shell read at each level) is the same as in one long run.
 int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
                  int64_t nt, int k, stencil_ctx::recording* rec) {
-    const size_t span = (size_t)field_span(g);
+    const field_layout FL = layout_of(g);
+    const size_t span = FL.span;
     const int n = (int)((nt + k - 1) / k);
-    const size_t need = 2 * (size_t)n * span * sizeof(float);
-    if (!rec->buf || rec->span * 2 * (size_t)rec->n * sizeof(float) < need) {
+    const size_t need = FL.bytes(2 * (size_t)n);
+    if (!rec->buf || rec->bytes < need) {
         if (rec->buf) ws_free(ctx, rec->buf);
         rec->buf = nullptr;
+        rec->bytes = 0;
         rec->valid = false;
         void* p = nullptr;
         int rc = ws_alloc(ctx, need, &p);
         if (rc) return rc;
-        rec->buf = static_cast<float*>(p);
+        rec->buf = p;
+        rec->bytes = need;
     }
     rec->valid = false;
-    rec->span = span;
+    rec->lead = FL.lead;
+    rec->stride = FL.stride;
     rec->n = n;
     for (int q = 0; q < n; ++q) {
         const int64_t t = (int64_t)q * k;
@@ -352,10 +379,10 @@ int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stenci
         stencil_grid sub = *g;
         sub.u[0] = g->u[t % 2];        // holds u_{t-1}
         sub.u[1] = g->u[(t + 1) % 2];  // holds u_t
-        hipError_t e = hipMemcpyAsync(rec->buf + (2 * (size_t)q) * span, sub.u[0],
+        hipError_t e = hipMemcpyAsync(FL.at(rec->buf, 2 * (size_t)q), sub.u[0],
                                       span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(rec->buf + (2 * (size_t)q + 1) * span, sub.u[1],
+            e = hipMemcpyAsync(FL.at(rec->buf, 2 * (size_t)q + 1), sub.u[1],
                                span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
         if (e != hipSuccess) return dev_fail(e, "checkpoint copy");
         const int rc = ctx->scheme == STENCIL_NAIVE ? run_naive(ctx, kind, &sub, c, steps)
@@ -399,22 +426,24 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
         return e == hipSuccess ? STENCIL_OK : dev_fail(e, "adjoint (nt = 0)");
     }
     stencil_ctx::recording& rec = ctx->rec;
-    const size_t span = (size_t)field_span(g);
+    const field_layout FL = layout_of(g);
+    const size_t span = FL.span;
     int rc;
     if (!recording_matches(rec, g, c, nt)) {
         // no usable recording: rerun the forward from the initial state held by
         // the caller's buffers, on workspace copies
         void* p = nullptr;
-        rc = ws_alloc(ctx, 2 * span * sizeof(float), &p);
+        rc = ws_alloc(ctx, FL.bytes(2), &p);
         if (rc) return rc;
-        float* w = static_cast<float*>(p);
-        e = hipMemcpyAsync(w, g->u[0], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+        float* w0 = FL.at(p, 0);
+        float* w1 = FL.at(p, 1);
+        e = hipMemcpyAsync(w0, g->u[0], span * sizeof(float), hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(w + span, g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+            e = hipMemcpyAsync(w1, g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return dev_fail(e, "adjoint forward copy");
         stencil_grid wg = *g;
-        wg.u[0] = w;
-        wg.u[1] = w + span;
+        wg.u[0] = w0;
+        wg.u[1] = w1;
         const int k = ctx->tuning.ckpt_every > 0 ? ctx->tuning.ckpt_every : default_ckpt(nt);
         rc = run_recorded(ctx, 5, &wg, c, nt, k, &rec);
         // the recording describes the caller's grid (same sizes and strides)
@@ -428,18 +457,17 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
     // read from the checkpoint itself), two adjoint fields and a flag
     void* p = nullptr;
     const size_t nslot = (size_t)(k > 1 ? k - 1 : 0);
-    rc = ws_alloc(ctx, (nslot + 2) * span * sizeof(float) + 256, &p);
+    rc = ws_alloc(ctx, FL.bytes(nslot + 3), &p);
     if (rc) return rc;
-    float* ws = static_cast<float*>(p);
-    float* lam_a = ws + nslot * span;
-    float* lam_b = lam_a + span;
-    int* flag = reinterpret_cast<int*>(lam_b + span);
+    float* lam_a = FL.at(p, nslot);
+    float* lam_b = FL.at(p, nslot + 1);
+    int* flag = reinterpret_cast<int*>(FL.at(p, nslot + 2));
     const float* seg0 = nullptr;  // checkpoint of the current segment: u_{a-1}, u_a
     const float* seg1 = nullptr;
     auto slot = [&](int i) -> float* {
         if (i == 0) return const_cast<float*>(seg0);
         if (i == 1) return const_cast<float*>(seg1);
-        return ws + (size_t)(i - 2) * span;
+        return FL.at(p, (size_t)(i - 2));
     };
     auto done = [&](hipError_t err, const char* what) {
         const hipError_t es = hipStreamSynchronize(st);
@@ -458,8 +486,9 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
     // the boundary shell is taken as time independent: every slot gets the
     // shell of the buffer holding level 0 (its interior is overwritten)
     for (size_t i = 0; i < nslot && e == hipSuccess; ++i)
-        e = hipMemcpyAsync(ws + i * span, g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = stn::launch_zero_span(lam_a, 2 * span, st);
+        e = hipMemcpyAsync(FL.at(p, i), g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = stn::launch_zero_span(lam_a, span, st);
+    if (e == hipSuccess) e = stn::launch_zero_span(lam_b, span, st);
     if (e == hipSuccess)
         e = mu ? stn::launch_mul_coef(lam_a, seed, bf16, c->arrays, d, st)
                : stn::launch_scale_copy(lam_a, seed, 1.0f, d, st);
@@ -483,8 +512,8 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
     for (int q = rec.n - 1; q >= 0 && e == hipSuccess; --q) {
         const int64_t a = (int64_t)q * k;
         const int64_t b = std::min<int64_t>(a + k, nt);
-        seg0 = rec.buf + (2 * (size_t)q) * span;
-        seg1 = seg0 + span;
+        seg0 = rec.field(2 * (size_t)q);
+        seg1 = rec.field(2 * (size_t)q + 1);
         // slot i holds u_{a-1+i}
         for (int64_t i = 1; i + a < b && e == hipSuccess; ++i)
             e = stn::launch_naive_step(5, bf16, slot((int)i), slot((int)i - 1), slot((int)i + 1),
