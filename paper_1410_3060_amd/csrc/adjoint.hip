@@ -30,6 +30,8 @@
 // load and a step without gradient terms is the forward kernel.  The
 // gradient is then accumulated as sum mu_{n+1} L8(u_n) and divided by c once
 // at the end, as are lambda_0 = mu_0 / c and lambda_1 = mu_1 / c.
+#include <type_traits>
+
 #include "adjoint.h"
 #include "common.h"
 #include "point_ops.h"
@@ -46,7 +48,7 @@ struct w64 {
 };
 
 // TERMS: bit 0 the term of step m+1, bit 1 of step m, bit 2 of step m-1.
-template <typename CT, int NW, int RPT, int TERMS, bool MU>
+template <typename CT, int NW, int RPT, int TERMS, bool MU, bool D64>
 __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
     const float* __restrict__ lam1, float* lam2, const CT* __restrict__ coef,
     const float* u_p, const float* u_c, const float* u_n, double* __restrict__ g, int nx, int ny,
@@ -59,7 +61,11 @@ __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
     constexpr int LW = 64 + 2 * R;
     constexpr int LH = TY + 2 * R;
     constexpr int HYJ = (2 * R + NW - 1) / NW;
-    __shared__ float lds[F][2][LH][LW];
+    // the u planes are staged in FP64 (D64) or FP32: FP64 staging converts
+    // each value once instead of at each of its stencil uses
+    using UT = typename std::conditional<D64, double, float>::type;
+    __shared__ float ldv[2][LH][LW];
+    __shared__ UT ldu[NUA][2][LH][LW];
 
     const int tile = xcd_remap(blockIdx.x, ntiles);
     const int bx = tile % gx;
@@ -236,21 +242,21 @@ __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
             l2c[i] = l2n[i];
             cpt[i] = MU ? ncp[i] : 0.0f;
             gc[i] = NU > 0 ? gn[i] : 0.0;
-            lds[0][b][R + wv + NW * i][R + lane] = qv[i][R];
+            ldv[b][R + wv + NW * i][R + lane] = qv[i][R];
 #pragma unroll
-            for (int f = 0; f < NU; ++f) lds[1 + f][b][R + wv + NW * i][R + lane] = qu[f][i][R];
+            for (int f = 0; f < NU; ++f) ldu[f][b][R + wv + NW * i][R + lane] = (UT)qu[f][i][R];
         }
 #pragma unroll
         for (int j = 0; j < HYJ; ++j)
             if (wv + NW * j < 2 * R) {
-                lds[0][b][hrow[j]][R + lane] = hv[j];
+                ldv[b][hrow[j]][R + lane] = hv[j];
 #pragma unroll
-                for (int f = 0; f < NU; ++f) lds[1 + f][b][hrow[j]][R + lane] = hu[f][j];
+                for (int f = 0; f < NU; ++f) ldu[f][b][hrow[j]][R + lane] = (UT)hu[f][j];
             }
         if (hx_any) {
-            lds[0][b][hx_ly][hx_lx] = xv;
+            ldv[b][hx_ly][hx_lx] = xv;
 #pragma unroll
-            for (int f = 0; f < NU; ++f) lds[1 + f][b][hx_ly][hx_lx] = xu[f];
+            for (int f = 0; f < NU; ++f) ldu[f][b][hx_ly][hx_lx] = (UT)xu[f];
         }
         if (z + 1 < z1) fetch(z + 1);
         __syncthreads();
@@ -261,8 +267,8 @@ __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
             n.c = qv[i][R];
 #pragma unroll
             for (int r = 1; r <= R; ++r) {
-                n.pair[0][r - 1] = lds[0][b][ly][lx - r] + lds[0][b][ly][lx + r];
-                n.pair[1][r - 1] = lds[0][b][ly - r][lx] + lds[0][b][ly + r][lx];
+                n.pair[0][r - 1] = ldv[b][ly][lx - r] + ldv[b][ly][lx + r];
+                n.pair[1][r - 1] = ldv[b][ly - r][lx] + ldv[b][ly + r][lx];
                 n.pair[2][r - 1] = qv[i][R - r] + qv[i][R + r];
             }
             const float lam1c = MU ? qv[i][R] : qr[i][0];
@@ -283,9 +289,9 @@ __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
 #pragma unroll
                     for (int r = 1; r <= R; ++r) {
                         const double px =
-                            (double)lds[1 + f][b][ly][lx - r] + (double)lds[1 + f][b][ly][lx + r];
+                            (double)ldu[f][b][ly][lx - r] + (double)ldu[f][b][ly][lx + r];
                         const double py =
-                            (double)lds[1 + f][b][ly - r][lx] + (double)lds[1 + f][b][ly + r][lx];
+                            (double)ldu[f][b][ly - r][lx] + (double)ldu[f][b][ly + r][lx];
                         const double pz = (double)qu[f][i][R - r] + (double)qu[f][i][R + r];
                         lu = __builtin_fma(wd.w[r], (px + py) + pz, lu);
                     }
@@ -385,25 +391,23 @@ int util_blocks(const dims& d) {
 
 namespace {
 
-template <typename CT, int NW, int RPT, int TERMS, bool MU>
+template <typename CT, int NW, int RPT, int TERMS, bool MU, bool D64>
 hipError_t launch_terms(const float* lam1, float* lam2, const CT* coef, const float* up,
                         const float* uc, const float* un, double* g, const dims& d,
                         const weights& wt, const w64& wd, int zchunk, hipStream_t s) {
     constexpr int TY = NW * RPT;
     const int gx = (d.nx + 63) / 64, gy = (d.ny + TY - 1) / TY;
-    if (zchunk <= 0) {
-        // about 2048 workgroups, chunks of at least 4R planes
-        const long long txy = (long long)gx * gy;
-        long long nzc = (2048 + txy - 1) / txy;
-        zchunk = (int)((d.nz + nzc - 1) / nzc);
-        if (zchunk < 4 * R) zchunk = 4 * R;
-        if (zchunk > d.nz) zchunk = d.nz;
-    }
+    if (zchunk <= 0)
+        zchunk = pick_zchunk(
+            d.nz, (long long)gx * gy,
+            device_slots(reinterpret_cast<const void*>(&adjoint_step_kernel<CT, NW, RPT, TERMS, MU, D64>),
+                         NW * 64),
+            R);
     const int gz = (d.nz + zchunk - 1) / zchunk;
     const long long ntiles = (long long)gx * gy * gz;
     if (ntiles <= 0) return hipSuccess;
     if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((adjoint_step_kernel<CT, NW, RPT, TERMS, MU>), dim3((unsigned)ntiles),
+    hipLaunchKernelGGL((adjoint_step_kernel<CT, NW, RPT, TERMS, MU, D64>), dim3((unsigned)ntiles),
                        dim3(NW * 64), 0,
                        s, lam1, lam2, coef, up, uc, un, g, d.nx, d.ny, d.nz, d.sy, d.sz, d.org(),
                        wt, wd, zchunk, gx, gy, (int)ntiles);
@@ -415,20 +419,20 @@ hipError_t launch_ct(const float* lam1, float* lam2, const CT* coef, const float
                      const float* uc, const float* un, double* g, const dims& d, const weights& wt,
                      const w64& wd, int zchunk, hipStream_t s) {
     const int terms = (up ? 1 : 0) | (uc ? 2 : 0) | (un ? 4 : 0);
-#define STN_ADJ_CASE(T, NW, RPT)                                                           \
-    case T:                                                                                \
-        return launch_terms<CT, NW, RPT, T, MU>(lam1, lam2, coef, up, uc, un, g, d, wt, wd, \
-                                                zchunk, s)
-    // waves per workgroup and rows per lane by term count (registers: one
-    // 2R+1 queue per stencil field and row)
+#define STN_ADJ_CASE(T, NW, RPT, D64)                                                        \
+    case T:                                                                                  \
+        return launch_terms<CT, NW, RPT, T, MU, D64>(lam1, lam2, coef, up, uc, un, g, d, wt, wd, \
+                                                     zchunk, s)
+    // waves per workgroup, rows per lane and FP64 staging of the u planes by
+    // term set (registers: one 2R+1 queue per stencil field and row)
     switch (terms) {
-        STN_ADJ_CASE(0, 4, 4);
-        STN_ADJ_CASE(1, 4, 2);
-        STN_ADJ_CASE(2, 4, 2);
-        STN_ADJ_CASE(3, 4, 2);
-        STN_ADJ_CASE(4, 4, 2);
-        STN_ADJ_CASE(6, 4, 2);
-        STN_ADJ_CASE(7, 4, 2);
+        STN_ADJ_CASE(0, 4, 4, false);
+        STN_ADJ_CASE(1, 4, 2, false);
+        STN_ADJ_CASE(2, 4, 2, false);
+        STN_ADJ_CASE(3, 4, 2, false);
+        STN_ADJ_CASE(4, 4, 2, false);
+        STN_ADJ_CASE(6, 4, 2, false);
+        STN_ADJ_CASE(7, 4, 2, false);
     default: return hipErrorInvalidValue;
     }
 #undef STN_ADJ_CASE

@@ -29,6 +29,17 @@ hipError_t launch_naive_step(int kind, bool coef_bf16, const float* cur, const f
 // Planes per z-chunk the naive launcher picks when zchunk == 0.
 int naive_default_zchunk(int kind, const dims& d);
 
+// Workgroups of `kernel` (with `threads` threads) resident on the current
+// device at once: its occupancy per compute unit times the compute units.
+long long device_slots(const void* kernel, int threads);
+
+// Planes per z-chunk for a streaming kernel with txy workgroups per z-chunk
+// and stencil radius R, given `slots` resident workgroups: the chunk count
+// minimises (rounds of resident workgroups) x (planes a workgroup streams,
+// its chunk plus the 2R planes that prime its register queues) -- the time of
+// a bandwidth-bound launch whose workgroups stream equal chunks.
+int pick_zchunk(int nz, long long txy, long long slots, int R);
+
 // Copy the boundary shell of width r (every point of [-r, n+r)^3 outside the
 // interior) from src to dst; interior points of dst are not touched.
 hipError_t launch_copy_shell(float* dst, const float* src, const dims& d, int r, hipStream_t s);

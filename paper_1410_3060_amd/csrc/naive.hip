@@ -8,6 +8,9 @@
 // of width R is staged in LDS (double buffered, one barrier per plane) for the
 // in-plane neighbours.  x is the lane index, so every global access of a wave
 // is one contiguous 256-byte row.  Coefficients are read once per point.
+#include <mutex>
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 #include "point_ops.h"
@@ -223,18 +226,68 @@ hipError_t launch_copy_shell(float* dst, const float* src, const dims& d, int r,
     return hipGetLastError();
 }
 
+long long device_slots(const void* kernel, int threads) {
+    // cached per (kernel, device): occupancy queries cost host time per launch
+    struct entry {
+        const void* k;
+        int dev, threads;
+        long long slots;
+    };
+    static std::mutex mu;
+    static std::vector<entry> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const entry& e : cache)
+            if (e.k == kernel && e.dev == dev && e.threads == threads) return e.slots;
+    }
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const long long slots = (long long)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({kernel, dev, threads, slots});
+    return slots;
+}
+
+int pick_zchunk(int nz, long long txy, long long slots, int R) {
+    if (nz <= 0) return 1;
+    if (txy <= 0 || slots <= 0) return nz;
+    int best = nz;
+    long long best_cost = -1;
+    for (int gz = 1; gz <= nz; ++gz) {
+        const int zc = (nz + gz - 1) / gz;
+        const long long wgs = txy * ((nz + zc - 1) / zc);
+        if (wgs > 0x7fffffffLL) break;
+        const long long rounds = (wgs + slots - 1) / slots;
+        const long long cost = rounds * (zc + 2 * R);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = zc;
+        }
+        if (zc == 1) break;
+    }
+    return best;
+}
+
 int naive_default_zchunk(int kind, const dims& d) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;
-    const int TY = NW * (R == 1 ? 8 : 4);
+    const int RPT = R == 1 ? 8 : 4;
+    const int TY = NW * RPT;
     const long long txy = (long long)((d.nx + 63) / 64) * ((d.ny + TY - 1) / TY);
-    // aim at >= 2048 workgroups (8 per CU) with chunks of at least 4R planes
-    // (a chunk re-reads 2R planes of the stencil operand, mostly from L2)
-    long long nzc = (2048 + txy - 1) / (txy > 0 ? txy : 1);
-    if (nzc < 1) nzc = 1;
-    int zc = (int)((d.nz + nzc - 1) / nzc);
-    if (zc < 4 * R) zc = 4 * R;
-    if (zc > d.nz) zc = d.nz > 0 ? d.nz : 1;
-    return zc;
+    const void* k = nullptr;
+    switch (kind) {
+    case 1: k = reinterpret_cast<const void*>(&naive_step_kernel<1, float, 8>); break;
+    case 2: k = reinterpret_cast<const void*>(&naive_step_kernel<2, float, 8>); break;
+    case 3: k = reinterpret_cast<const void*>(&naive_step_kernel<3, float, 4>); break;
+    case 4: k = reinterpret_cast<const void*>(&naive_step_kernel<4, float, 4>); break;
+    default: k = reinterpret_cast<const void*>(&naive_step_kernel<5, float, 4>); break;
+    }
+    return pick_zchunk(d.nz, txy, device_slots(k, NT), R);
 }
 
 hipError_t launch_naive_step(int kind, bool bf16, const float* cur, const float* prev, float* out,
