@@ -29,9 +29,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={A
 
 def _compile(src: str, src_dir: str, build_dir: str) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    # abi.cpp is host code (HIP runtime API only); the .hip files hold the kernels
     cmd = [HIPCC] + COMMON + ["-c", os.path.join(src_dir, src), "-o", obj]
-    if src.endswith(".cpp"):
-        cmd += ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -397,12 +397,12 @@ hipError_t launch_terms(const float* lam1, float* lam2, const CT* coef, const fl
                         const weights& wt, const w64& wd, int zchunk, hipStream_t s) {
     constexpr int TY = NW * RPT;
     const int gx = (d.nx + 63) / 64, gy = (d.ny + TY - 1) / TY;
-    if (zchunk <= 0)
-        zchunk = pick_zchunk(
-            d.nz, (long long)gx * gy,
-            device_slots(reinterpret_cast<const void*>(&adjoint_step_kernel<CT, NW, RPT, TERMS, MU, D64>),
-                         NW * 64),
-            R);
+    if (zchunk <= 0) {
+        const long long slots = device_slots(
+            reinterpret_cast<const void*>(&adjoint_step_kernel<CT, NW, RPT, TERMS, MU, D64>),
+            NW * 64);
+        zchunk = pick_zchunk(d.nz, (long long)gx * gy, slots, R);
+    }
     const int gz = (d.nz + zchunk - 1) / zchunk;
     const long long ntiles = (long long)gx * gy * gz;
     if (ntiles <= 0) return hipSuccess;
