@@ -373,15 +373,15 @@ hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
         if (H == 4) return launch_cfg<KIND, CT, 4, 10, 1, true>(a, s);
         if (H == 6) return launch_cfg<KIND, CT, 6, 14, 1, true, false, 1>(a, s);
     } else if constexpr (KIND == 5) {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 2, true, true, 1>(a, s);
+        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, true, true, 1>(a, s);
     } else {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 2, false, true, 1>(a, s);
+        if (H == 2) return launch_cfg<KIND, CT, 2, 16, 2, false, true, 1>(a, s);
     }
     return hipErrorInvalidValue;
 }
 
 // x chunks of the configuration above (host side)
-int cfg_xch(int kind, int H) { return (kind == 2 && (H == 4 || H == 6)) ? 1 : 2; }
+int cfg_xch(int kind, int H) { return ((kind == 2 && (H == 4 || H == 6)) || kind == 5) ? 1 : 2; }
 
 }  // namespace
 
