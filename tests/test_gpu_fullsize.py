@@ -1,0 +1,134 @@
+"""Full-size checks: every workload at its real size and nt, in the launch
+configuration bench.py times (default diamond width, default chunks).
+
+* blocked == naive bit for bit over the whole grid (FP32 and BF16 coefficients);
+* the last step, sampled: the GPU's level nt at 3000 seeded interior points
+  (faces, edges and corners included) against the oracle's single update of
+  the GPU's own levels nt-1 (and nt-2), point by point;
+* the adjoint of workload 5 (256^3, 200 steps, checkpoints every 14): the
+  dot-product identity <F(d), s> = <d_{-1}, g_{-1}> + <d_0, g_0> for the linear
+  map F: (u_{-1}, u_0) -> u_T, which holds at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1410_3060_amd as st
+import workloads
+
+from gpu_util import coef_to_dev, gpu_weights, oracle_weights, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def sample_points(n3, count, seed):
+    rng = np.random.default_rng([1410, 99, seed])
+    nx, ny, nz = n3
+    pts = np.stack([rng.integers(0, nx, count), rng.integers(0, ny, count),
+                    rng.integers(0, nz, count)], axis=1)
+    # pin some to the faces, edges and corners
+    k = count // 10
+    pts[:k, 0] = rng.choice([0, nx - 1], k)
+    pts[k:2 * k, 1] = rng.choice([0, ny - 1], k)
+    pts[2 * k:3 * k, 2] = rng.choice([0, nz - 1], k)
+    pts[3 * k:3 * k + 8] = [[x, y, z] for x in (0, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1)]
+    return pts
+
+
+def host(t):
+    return t.detach().cpu().contiguous().numpy()
+
+
+def run_levels(wl, scheme, nt, coef, **kw):
+    """Run nt steps from the workload's initial state; returns (newest, previous) device fields."""
+    h = wl.halo
+    if wl.kind in (4, 5):
+        a, b = to_dev(wl.u_prev, h), to_dev(wl.u0, h)
+    else:
+        a, b = to_dev(wl.u0, h), to_dev(np.zeros_like(wl.u0), h)
+    with st.Context(scheme, **kw) as ctx:
+        slot = ctx.run(wl.kind, a, b, nt, halo=h, coef=coef, w=gpu_weights(wl), alpha=wl.alpha)
+        ctx.sync()
+    return (a, b)[slot], (a, b)[1 - slot]
+
+
+@pytest.mark.parametrize("index", [1, 2, 3, 4, 5])
+def test_fullsize_blocked_equals_naive_and_last_step(index):
+    import torch
+    wl = workloads.make(index)
+    h, nt = wl.halo, wl.nt
+    cf = coef_to_dev(wl)
+    top_n, prev_n = run_levels(wl, st.NAIVE, nt, cf)
+    top_b, prev_b = run_levels(wl, st.BLOCKED, nt, cf)
+    assert torch.equal(top_n, top_b), "blocked and naive differ at level nt"
+    if wl.kind in (4, 5):
+        assert torch.equal(prev_n, prev_b), "blocked and naive differ at level nt-1"
+    got = host(top_n).astype(np.float64)
+    del top_b, prev_b
+    # levels nt-1 (and nt-2) from a run of nt-1 steps
+    l1, l2 = run_levels(wl, st.NAIVE, nt - 1, cf)
+    u1 = host(l1)
+    u2 = host(l2) if wl.kind in (4, 5) else None
+    if wl.kind in (4, 5):
+        # the two runs share levels: nt-1 of the long run is the top of the short one
+        assert np.array_equal(host(prev_n), u1)
+    pts = sample_points(wl.n3, 3000, index)
+    coef = wl.coef_values_f32() if wl.coef is not None else None
+    want = oracle.step_points(wl.kind, u1, h, pts, u_prev=u2, coef=coef, w=oracle_weights(wl),
+                              alpha=wl.alpha)
+    x, y, z = pts[:, 0] + h, pts[:, 1] + h, pts[:, 2] + h
+    gv = got[z, y, x]
+    # FP32 bound: each update sums at most ~30 rounded terms whose magnitudes
+    # are bounded by (sum of |weights| + 3) times the largest |u| nearby
+    R = oracle.RADIUS[wl.kind]
+    scale = np.array([np.abs(u1[zz - R:zz + R + 1, yy - R:yy + R + 1, xx - R:xx + R + 1]).max()
+                      for xx, yy, zz in zip(x, y, z)])
+    err = np.abs(gv - want)
+    print(f"{wl.name}: sampled last step, max err/scale {np.max(err / np.maximum(scale, 1e-30)):.2e}")
+    assert np.all(err <= 2e-5 * np.maximum(scale, 1e-30))
+
+
+@pytest.mark.parametrize("index", [3, 4])
+def test_fullsize_bf16_blocked_equals_naive(index):
+    import torch
+    wl = workloads.make(index, coef_dtype="bf16")
+    cf = coef_to_dev(wl)
+    top_n, _ = run_levels(wl, st.NAIVE, wl.nt, cf)
+    top_b, _ = run_levels(wl, st.BLOCKED, wl.nt, cf)
+    assert torch.equal(top_n, top_b)
+
+
+def test_fullsize_adjoint_dot_product():
+    import torch
+    wl = workloads.make(5)
+    h, nt = wl.halo, wl.nt
+    rng = np.random.default_rng([1410, 98, 5])
+    shape = wl.u0.shape
+    inner = (slice(h, -h),) * 3
+
+    def field(scale):
+        a = np.zeros(shape, dtype=np.float32)
+        a[inner] = (scale * rng.uniform(-1, 1, tuple(s - 2 * h for s in shape))).astype(np.float32)
+        return a
+
+    dm1, d0, s = field(1.0), field(1.0), field(1.0)
+    c = st.alloc_field(wl.n3, h, count=1)
+    c.copy_(torch.from_numpy(wl.coef))
+    a, b = to_dev(dm1, h), to_dev(d0, h)
+    up, u0 = to_dev(dm1, h), to_dev(d0, h)
+    with st.Context(st.NAIVE, ckpt_every=workloads.CKPT_EVERY) as ctx:
+        slot = ctx.run(5, a, b, nt, halo=h, coef=c, w=st.L8_WEIGHTS)
+        seed = to_dev(s, h)
+        g0, gm1 = st.alloc_field(wl.n3, h), st.alloc_field(wl.n3, h)
+        gc = st.alloc_field(wl.n3, h, dtype=torch.float64)
+        ctx.adjoint(up, u0, nt, halo=h, coef=c, w=st.L8_WEIGHTS, seed=seed, grad_u0=g0,
+                    grad_um1=gm1, grad_c=gc)
+        ctx.sync()
+    uT = host((a, b)[slot]).astype(np.float64)
+    lhs = float(np.sum(uT[inner] * s[inner].astype(np.float64)))
+    rhs = float(np.sum(host(gm1).astype(np.float64)[inner] * dm1[inner]) +
+                np.sum(host(g0).astype(np.float64)[inner] * d0[inner]))
+    rel = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    print(f"adjoint dot product 256^3 nt=200: <F d, s> = {lhs:.9e}, <d, F^T s> = {rhs:.9e}, "
+          f"rel {rel:.2e}")
+    assert rel <= 1e-5
