@@ -34,23 +34,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def blocked_bytes_per_lup(K, H, R, coef_bytes=4, field_bytes=4):
-    """Algorithmic HBM bytes per lattice update of the blocked scheme.
-
-    Per diamond of width dw = 2RH and per (x, z) column: the old frontier is
-    read (two levels) on dw + 2R cells, K coefficients on dw cells, the new
-    frontier written (two levels) on dw cells; the diamond performs dw*H
-    updates there.  So B = [2(dw+2R) f + K dw c + 2 dw f] / (dw H).
-    """
-    dw = 2 * R * H
-    return (2 * (dw + 2 * R) * field_bytes + K * dw * coef_bytes + 2 * dw * field_bytes) / (dw * H)
-
-
-def naive_bytes_per_lup(K, leapfrog, coef_bytes=4, field_bytes=4):
-    """One read of u, K coefficients, one write (+ u_{n-1} read for the leapfrog)."""
-    return field_bytes * (2 + (1 if leapfrog else 0)) + K * coef_bytes
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +61,7 @@ def main():
 
     import paper_1410_3060_amd as st
     import workloads
+    from paper_1410_3060_amd import model
 
     st.load()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
@@ -137,7 +121,7 @@ def main():
     value = lups / t_step / 1e9
     log(f"[bench] blocked: {t_step * 1e3:.2f} ms per run, {value:.1f} GLUP/s")
 
-    bpl_b = blocked_bytes_per_lup(K, H, R)
+    bpl_b = model.blocked_bytes_per_lup(st.KIND_25PT_VAR, args.dw)
     # average row-launch duration from the same HIP events (launch gaps included)
     avg_launch = t_step / n_rows
     achieved = bpl_b * lups / n_rows / avg_launch / 1e9
@@ -156,7 +140,7 @@ def main():
         ctx_n = st.Context(st.NAIVE, stream=stream)
         tn = timed(ctx_n, coef32, max(2, args.steps // 2), 1)
         tn_s = float(np.median(tn))
-        bpl_n = naive_bytes_per_lup(K, False)
+        bpl_n = model.naive_code_balance(st.KIND_25PT_VAR)
         extras["naive"] = {"glups": round(lups / tn_s / 1e9, 2), "ms_per_run": round(tn_s * 1e3, 3),
                            "bytes_per_lup": bpl_n,
                            "achieved_GBps": round(bpl_n * lups / tn_s / 1e9, 1)}
