@@ -1,18 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark: GLUP/s of the temporally blocked stencil scheme on one MI355X.
 
-Workload (the one the blocked-vs-naive target is stated for): the 25-point
-8th-order variable-coefficient axis-symmetric stencil (Fig. 1d of the paper),
-480^3 interior, halo 4, 13 FP32 coefficient arrays, 100 time steps, seeded
-synthetic inputs.  One benchmark "step" is one complete stencil_run of all
-100 time steps with the blocked scheme (diamond rows in y, wavefront in z),
+Workload: the 25-point 8th-order variable-coefficient axis-symmetric stencil
+(Fig. 1d of the paper), 480^3 interior, halo 4, 13 FP32 coefficient arrays,
+100 time steps, seeded synthetic inputs.  One benchmark "step" is one complete
+stencil_run of all 100 time steps with the blocked scheme (diamond rows in y,
+wavefront in z; --scheme naive times the one-sweep-per-step scheme instead),
 inputs resident in HBM.  value = lattice-site updates per second, counting
 only the algorithmic 480^3 * 100 updates (never recomputed halos).
 
-Beside it the same run is timed with the naive scheme (the baseline of the
-2x target), with BF16 coefficients, and the leapfrog adjoint workload
-(256^3, 200 steps) is timed forward and backward.  The FP64 CPU oracle is
-timed on a bounded sample of the same workload on the host cores.
+Beside it the other scheme is timed on the same run, both with BF16
+coefficients, and the leapfrog adjoint workload (256^3, 200 steps,
+checkpoints every 14) forward and backward.  The FP64 CPU oracle is timed on
+a bounded sample of the same workload on the host cores.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -39,10 +39,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scheme", choices=("blocked", "naive"), default="blocked",
+                    help="scheme of the timed run (the other one is timed among the extras)")
     ap.add_argument("--dw", type=int, default=16)
     ap.add_argument("--no-extras", action="store_true", help="skip naive/BF16/adjoint legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--n", type=int, default=None, help="override the grid size (testing only)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the adjoint leg (forward with checkpoints, then the adjoint)")
@@ -51,9 +53,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the path "
-              "would shard along y with whole diamonds per GPU, which is not built here.",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the multi-GPU path (y bands of "
+              "whole diamonds per GPU) is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -110,42 +111,50 @@ def main():
                 times.append(e0.elapsed_time(e1) / 1e3)
         return times
 
-    R, K = 4, 13
-    H = args.dw // (2 * R)
-    n_rows = len(st.plan_rows(3, args.dw, ny, nt))
-
-    log(f"[bench] blocked dw={args.dw}: {n_rows} row launches per run")
+    blocked = args.scheme == "blocked"
+    if blocked:
+        n_launch = len(st.plan_rows(st.KIND_25PT_VAR, args.dw, ny, nt))
+        bpl = model.blocked_bytes_per_lup(st.KIND_25PT_VAR, args.dw)
+        kname = "blocked_row_kernel<3, float, H=%d>" % (args.dw // 8)
+        tkey = "blocked_row_kernel"
+    else:
+        n_launch = nt
+        bpl = model.naive_code_balance(st.KIND_25PT_VAR)
+        kname = "naive_step_kernel<3, float, 4>"
+        tkey = "naive_step_kernel"
+    log(f"[bench] {args.scheme}: {n_launch} kernel launches per run")
     ctx_b = st.Context(st.BLOCKED, dw=args.dw, stream=stream)
-    tb = timed(ctx_b, coef32, args.steps, args.warmup)
+    ctx_n = st.Context(st.NAIVE, stream=stream)
+    tb = timed(ctx_b if blocked else ctx_n, coef32, args.steps, args.warmup)
     t_step = float(np.median(tb))
     value = lups / t_step / 1e9
-    log(f"[bench] blocked: {t_step * 1e3:.2f} ms per run, {value:.1f} GLUP/s")
+    log(f"[bench] {args.scheme}: {t_step * 1e3:.2f} ms per run, {value:.1f} GLUP/s")
 
-    bpl_b = model.blocked_bytes_per_lup(st.KIND_25PT_VAR, args.dw)
-    # average row-launch duration from the same HIP events (launch gaps included)
-    avg_launch = t_step / n_rows
-    achieved = bpl_b * lups / n_rows / avg_launch / 1e9
-    traffic = measured_traffic(wl.name, args.dw)
+    # average launch duration of the dominant kernel from the same HIP events
+    # (launch gaps and the few small copies of a run included)
+    avg_launch = t_step / n_launch
+    achieved = bpl * lups / n_launch / avg_launch / 1e9
+    traffic = measured_traffic(tkey, wl.name, args.dw if blocked else 0)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 3),
                 "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-                "algorithmic_per_launch_GB": round(bpl_b * lups / n_rows / 1e9, 3),
-                "copy_probe_GBps": probe["GBps"],
-                "kernel": "blocked_row_kernel<3,float,H=%d>" % H,
-                "bytes_per_lup": round(bpl_b, 3), "avg_launch_ms": round(avg_launch * 1e3, 4)}
+                "algorithmic_per_launch_GB": round(bpl * lups / n_launch / 1e9, 3),
+                "copy_probe_GBps": probe["GBps"], "kernel": kname,
+                "bytes_per_lup": round(bpl, 3), "avg_launch_ms": round(avg_launch * 1e3, 4)}
 
     extras = {}
     if not args.no_extras:
-        ctx_n = st.Context(st.NAIVE, stream=stream)
-        tn = timed(ctx_n, coef32, max(2, args.steps // 2), 1)
-        tn_s = float(np.median(tn))
-        bpl_n = model.naive_code_balance(st.KIND_25PT_VAR)
-        extras["naive"] = {"glups": round(lups / tn_s / 1e9, 2), "ms_per_run": round(tn_s * 1e3, 3),
-                           "bytes_per_lup": bpl_n,
-                           "achieved_GBps": round(bpl_n * lups / tn_s / 1e9, 1)}
-        extras["blocked_over_naive"] = round(tn_s / t_step, 3)
-        log(f"[bench] naive: {tn_s * 1e3:.2f} ms per run ({extras['naive']['glups']} GLUP/s)")
+        other = max(2, args.steps // 2)
+        tn_s = t_step if not blocked else float(np.median(timed(ctx_n, coef32, other, 1)))
+        tb_s = t_step if blocked else float(np.median(timed(ctx_b, coef32, other, 1)))
+        for name, t, b in (("naive", tn_s, model.naive_code_balance(st.KIND_25PT_VAR)),
+                           ("blocked", tb_s, model.blocked_bytes_per_lup(st.KIND_25PT_VAR, args.dw))):
+            extras[name] = {"glups": round(lups / t / 1e9, 2), "ms_per_run": round(t * 1e3, 3),
+                            "bytes_per_lup": round(b, 3),
+                            "algorithmic_GBps": round(b * lups / t / 1e9, 1)}
+        extras["blocked_over_naive"] = round(tn_s / tb_s, 3)
+        log(f"[bench] naive {extras['naive']['glups']}, blocked {extras['blocked']['glups']} GLUP/s")
         # BF16 coefficient storage
         bits = workloads.to_bf16_bits(wl.coef)
         coef16 = st.alloc_field(wl.n3, h, count=13, dtype=torch.bfloat16)
@@ -158,19 +167,19 @@ def main():
                           "blocked_over_naive": round(tn16 / tb16, 3)}
         log(f"[bench] bf16: blocked {lups / tb16 / 1e9:.1f}, naive {lups / tn16 / 1e9:.1f} GLUP/s")
         del coef16
-        ctx_n.close()
         try:
             extras["adjoint"] = adjoint_leg(st, workloads, torch, np, stream, args)
         except Exception as e:  # the adjoint leg reports, it does not sink the line
             extras["adjoint"] = {"error": str(e)[:200]}
     ctx_b.close()
+    ctx_n.close()
 
     cpu = None
     if not args.no_cpu:
         cpu = cpu_leg(wl, args.cpu_seconds)
 
     line = {
-        "metric": "GLUP/s (blocked 25pt var-coef 480^3, 100 steps) + HBM GB/s; blocked vs naive",
+        "metric": "GLUP/s (25pt var-coef 480^3, 100 steps) + HBM GB/s; blocked vs naive",
         "value": round(value, 2),
         "unit": "GLUP/s",
         "n_gpus": 1,
@@ -183,7 +192,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "kind": "25pt-var", "n": list(wl.n3), "halo": h, "nt": nt,
-                   "scheme": "blocked", "dw": args.dw, "coef_dtype": "f32",
+                   "scheme": args.scheme, "dw": args.dw if blocked else None, "coef_dtype": "f32",
                    "seed": [workloads.SEED_BASE, 4]},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -192,27 +201,22 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-KERNEL_SOURCES = ["paper_1410_3060_amd/csrc/blocked.hip", "paper_1410_3060_amd/csrc/blocked.h",
-                  "paper_1410_3060_amd/csrc/point_ops.h", "paper_1410_3060_amd/csrc/common.h",
-                  "paper_1410_3060_amd/csrc/kernels.h"]
-
-
-def measured_traffic(workload, dw):
-    """HBM bytes per launch of the blocked kernel from the committed rocprofv3
-    counter summary, or None when the kernel sources changed since the
-    counters were taken (or they were taken on another workload)."""
+def measured_traffic(key, workload, dw):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, or None when the kernel's sources changed since the counters were
+    taken (or they were taken on another workload)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
-        rec = json.load(open(path))["blocked_row_kernel"]
+        rec = json.load(open(path))[key]
     except (OSError, KeyError, ValueError):
         return None
     h = hashlib.sha256()
-    for f in rec.get("sources", KERNEL_SOURCES):
+    for f in rec["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest() != rec.get("source_sha256") or rec.get("workload") != workload or \
-            rec.get("dw") != dw:
+            rec.get("dw", 0) != dw:
         return None
     return float(rec["hbm_bytes_per_launch"])
 
