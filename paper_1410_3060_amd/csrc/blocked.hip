@@ -129,7 +129,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         outx[c] = x >= x0 && x < x0 + XO && x < nx;
     }
 
-    auto level_active = [&](int j, int z) {
+    auto level_active = [&](int j, int z) __attribute__((always_inline)) {
         const int t = t0 + j;
         return z >= max(z0 - R * (L - j), -R) && z < min(z1 + R * (L - j), nz + R) && t >= -1 &&
                t <= nt;
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     // in-plane plane of level 1 next step), pc = coefficients at plane s.
     float pt[PD][CPT], ps[PD][CPT], pl[PD][CPT], p0[PD][CPT], pc[PD][CPT][KR];
 
-    auto prefetch = [&](int s, auto slot) {
+    auto prefetch = [&](int s, auto slot) __attribute__((always_inline)) {
         constexpr int SL = decltype(slot)::value;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
@@ -194,10 +194,13 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const int s_begin = z0 - R * (L + 1);
     const int s_end = z1 + R * (L - 1);
 
-    auto step = [&](int s, auto par, auto xbt) {
+    // mode 0: interior tile; 1: tile reaching the x boundary; 2: interior tile
+    // at a step whose levels are all active and inside [0, nz) (no z logic)
+    auto step = [&](int s, auto par, auto mode) __attribute__((always_inline)) {
         constexpr int set = decltype(par)::value;  // LDS set read by step s
         constexpr int SL = PD == 2 ? set : 0;      // prefetch slot holding step s
-        constexpr bool XB = decltype(xbt)::value != 0;
+        constexpr bool XB = decltype(mode)::value == 1;
+        constexpr bool FAST = decltype(mode)::value == 2;
         float ft[CPT], fs[CPT], fl[CPT], f0n[CPT];
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
@@ -226,8 +229,10 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
 #pragma unroll
         for (int j = 0; j <= L; ++j) {
             const int z = s - (j - 1) * R;
-            const bool act = level_active(j, z);
-            const bool zin = z >= 0 && z < nz;
+            // in the fast range a level outside [-1, nt] in time is treated as
+            // active: no row computes it or reads it, so its values are unused
+            const bool act = FAST || level_active(j, z);
+            const bool zin = FAST || (z >= 0 && z < nz);
             const int64_t zo = (int64_t)z * sz;
             const int jq = j >= 1 ? j - 1 : 0;
             const float* P = lds[set][jq];
@@ -327,12 +332,30 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         __syncthreads();
     };
 
-    auto run = [&](auto xbt) {
+    auto run = [&](auto mode) __attribute__((always_inline)) {
         prefetch(s_begin, ic<0>{});
         if (PD == 2 && s_begin + 1 < s_end) prefetch(s_begin + 1, ic<PD - 1>{});
-        for (int s = s_begin; s < s_end; s += 2) {
-            step(s, ic<0>{}, xbt);
-            if (s + 1 < s_end) step(s + 1, ic<1>{}, xbt);
+        int s = s_begin;
+        if constexpr (decltype(mode)::value == 0) {
+            // steps in [f_lo, f_hi) put every level z_j = s - (j-1)R inside
+            // [0, nz) and inside its active window; they run in pairs that keep
+            // the LDS and prefetch parity of the stream
+            const int f_lo = max(z0, 0) + (L - 1) * R;
+            const int f_hi = min(s_end, nz - R);
+            const int s_a = s_begin + 2 * ((max(f_lo - s_begin, 0) + 1) / 2);
+            const int s_b = s_a + 2 * (max(f_hi - s_a, 0) / 2);
+            for (; s < s_a && s < s_end; s += 2) {
+                step(s, ic<0>{}, ic<0>{});
+                if (s + 1 < s_end) step(s + 1, ic<1>{}, ic<0>{});
+            }
+            for (; s < s_b; s += 2) {
+                step(s, ic<0>{}, ic<2>{});
+                step(s + 1, ic<1>{}, ic<2>{});
+            }
+        }
+        for (; s < s_end; s += 2) {
+            step(s, ic<0>{}, mode);
+            if (s + 1 < s_end) step(s + 1, ic<1>{}, mode);
         }
     };
     if (xb)
