@@ -272,6 +272,10 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
     const stn::diamond_plan plan = stn::make_plan(R, dw, g->ny, nt);
     const field_layout FL = layout_of(g);
     const size_t fbytes = FL.span * sizeof(float);
+    // the kernel addresses fields with 32-bit byte offsets below 2^31
+    if (fbytes >= ((size_t)1 << 31))
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "blocked scheme: a field spans %zu bytes, the limit is 2 GiB", fbytes);
     int rc = ensure_frontier(ctx, FL.bytes(2));
     if (rc) return rc;
     float* w0 = FL.at(ctx->frontier, 0);
@@ -324,6 +328,8 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         a.first_centre = row.first_centre;
         a.n_diamonds = row.n_diamonds;
         a.dw = dw;
+        a.field_bytes = (uint32_t)fbytes;
+        a.coef_bytes = (uint32_t)(FL.span * (bf16 ? 2 : 4));
         a.xo = xo;
         a.gx = gx;
         int zc = ctx->tuning.zchunk;

@@ -27,6 +27,8 @@ struct blocked_row_args {
     int gx;       // x tiles
     int zchunk;   // planes per z-chunk
     int gz;       // z-chunks
+    uint32_t field_bytes;  // bytes of one field from its padded origin (< 2^31)
+    uint32_t coef_bytes;   // bytes of one coefficient array from its padded origin
 };
 
 bool blocked_supported(int kind, int dw);

@@ -51,12 +51,37 @@ namespace {
 template <int N>
 using ic = std::integral_constant<int, N>;
 
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// Byte offset beyond every buffer the kernel touches (fields stay below
+// 2 GiB): a buffer load there returns 0 and a buffer store is dropped, so an
+// operand a row does not need costs neither a branch nor a memory access.
+constexpr uint32_t kNone = 0x80000000u;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(rsrc_t r, float v, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+// coefficient loads: FP32, or BF16 expanded exactly to FP32 (as load_coef)
+__device__ __forceinline__ float cload(const float*, rsrc_t r, uint32_t voff, uint32_t soff) {
+    return bload(r, voff, soff);
+}
+__device__ __forceinline__ float cload(const uint16_t*, rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0))
+                           << 16);
+}
+
 template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING, bool G0, int PD>
 __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const float* ftop_o, const float* fsub_o, float* ftop_n, float* fsub_n,
-    const CT* __restrict__ coef, int64_t sk, int nx, int ny, int nz, int64_t sy, int64_t sz,
-    int64_t org, weights wt, int t0, int nt, int first_centre, int XO, int gx, int zchunk, int gz,
-    int ntiles) {
+    const CT* __restrict__ coef, int64_t sk, int nx, int ny, int nz, int hh, int64_t sy,
+    int64_t sz, uint32_t field_bytes, uint32_t coef_bytes, weights wt, int t0, int nt,
+    int first_centre, int XO, int gx, int zchunk, int gz, int ntiles) {
     constexpr int R = kind_traits<KIND>::R;
     constexpr int K = kind_traits<KIND>::K;
     constexpr bool LF = kind_traits<KIND>::leapfrog;
@@ -69,6 +94,8 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     constexpr int CPT = (NCOL + NWV - 1) / NWV;
     constexpr int NR = CRING ? (L - 1) * R + 1 : 1;  // coefficient planes in the ring
     constexpr int KR = CRING ? kslots<KIND> : 1;
+    constexpr int NSH = L * R + 1;                   // planes in the shell ring
+    constexpr uint32_t CB = sizeof(CT);
     __shared__ float lds[2][L][YT * XT];
 
     const int tile = xcd_remap(blockIdx.x, ntiles);
@@ -82,17 +109,19 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const int lane = threadIdx.x & 63;
     const int wvu = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 
-    // Addressing relative to the tile corner (x0 - RL, y_c - RH - R, 0).
+    // Tile corner (x0 - RL, y_c - RH - R); all offsets are relative to the
+    // padded origin of the fields: row part (y+h)*sy + (x+h), plane part (z+h)*sz.
     const int ybase = yc - R * H - R;
     const int xbase = x0 - R * L;
-    const int64_t cb = org + (int64_t)ybase * sy + xbase;
-    const float* FT = ftop_o + cb;
-    const float* FS = fsub_o + cb;
-    float* NT_ = ftop_n + cb;
-    float* NS = fsub_n + cb;
-    const CT* W = coef ? coef + cb : nullptr;
-    // the interior origin: an always-valid address for loads not needed
-    const int64_t safe = -((int64_t)ybase * sy + xbase);
+    const rsrc_t rFT = make_rsrc(ftop_o, field_bytes);
+    const rsrc_t rFS = make_rsrc(fsub_o, field_bytes);
+    const rsrc_t rNT = make_rsrc(ftop_n, field_bytes);
+    const rsrc_t rNS = make_rsrc(fsub_n, field_bytes);
+    const uint32_t sz4 = (uint32_t)(sz * 4);
+    const uint32_t szc = (uint32_t)(sz * CB);
+    auto pf = [&](int z) { return (uint32_t)(z + hh) * sz4; };  // field plane bytes
+    auto pc_ = [&](int z) { return (uint32_t)(z + hh) * szc; };  // coefficient plane bytes
+    auto crs = [&](int k) { return make_rsrc(coef + (int64_t)k * sk, coef_bytes); };
     // the tile reaches outside [0, nx) in x: boundary columns hold the shell
     const bool xb = xbase < 0 || xbase + XT > nx;
 
@@ -102,8 +131,8 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     // the diamond computes levels jo+1 .. jn of the row (none off the diamond).
     int rt[CPT], jo[CPT], jn[CPT];
     bool own[CPT];
-    int off[CPT];   // yl*sy + column (clamped into the shell), relative to the tile corner
-    int lidx[CPT];  // LDS index of the column
+    uint32_t vf[CPT], vc[CPT];  // byte offsets of the column's row in a field / coefficient plane
+    int lidx[CPT];              // LDS index of the column
     bool xin[CPT], outx[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -123,7 +152,9 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         jo[c] = to - t0;
         jn[c] = tn - t0;
         const int xc = min(max(x, -R), nx + R - 1);
-        off[c] = yl * (int)sy + (xc - xbase);
+        const uint32_t e = rt[c] != 0 ? (uint32_t)((int64_t)(y + hh) * sy + (xc + hh)) : 0u;
+        vf[c] = e * 4u;
+        vc[c] = e * CB;
         lidx[c] = valid ? yl * XT + xl : 0;
         xin[c] = x >= 0 && x < nx;
         outx[c] = x >= x0 && x < x0 + XO && x < nx;
@@ -140,6 +171,10 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     float qv[L][CPT][Q];
     // coefficient ring: cr[c][i][k] = coefficient k at plane s - i
     float cr[CPT][NR][KR];
+    // shell ring: sh[c][i] = old frontier top at plane s + R - i, i.e. the value
+    // of level j at its plane is sh[c][jR] wherever that point is boundary
+    // shell (time independent), and for rows whose top is level 0 it is level 0
+    float sh[CPT][NSH];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
 #pragma unroll
@@ -150,12 +185,17 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         for (int i = 0; i < NR; ++i)
 #pragma unroll
             for (int k = 0; k < KR; ++k) cr[c][i][k] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NSH; ++i) sh[c][i] = 0.0f;
     }
     // Memory operands of step s, loaded PD steps ahead into slot (s - s_begin) % PD:
     // pt/ps = old frontier top/sub at their planes, pl = u_{t0-1} at plane s
     // (leapfrog rows that compute level 1), p0 = level 0 at plane s+1 (G0: the
-    // in-plane plane of level 1 next step), pc = coefficients at plane s.
-    float pt[PD][CPT], ps[PD][CPT], pl[PD][CPT], p0[PD][CPT], pc[PD][CPT][KR];
+    // in-plane plane of level 1 next step), pp = level 0 at plane s - R of rows
+    // whose top is level 1 (G0 leapfrog: the older level of their level 2),
+    // ph = the shell ring's input at plane s + R, pc = coefficients at plane s.
+    float pt[PD][CPT], ps[PD][CPT], pl[PD][CPT], p0[PD][CPT], pp[PD][CPT], ph[PD][CPT];
+    float pc[PD][CPT][KR];
 
     auto prefetch = [&](int s, auto slot) __attribute__((always_inline)) {
         constexpr int SL = decltype(slot)::value;
@@ -165,28 +205,40 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             const int zt = s - (jo[c] - 1) * R, zs = s - (jo[c] - 2) * R;
             const bool okt = intr && jo[c] <= L && zt >= 0 && zt < nz && level_active(jo[c], zt);
             const bool oks = intr && jo[c] >= 1 && zs >= 0 && zs < nz && level_active(jo[c] - 1, zs);
-            const float a = FT[okt ? (int64_t)zt * sz + off[c] : safe];
-            const float b = FS[oks ? (int64_t)zs * sz + off[c] : safe];
-            pt[SL][c] = a;
-            ps[SL][c] = b;
+            pt[SL][c] = bload(rFT, okt ? vf[c] : kNone, okt ? pf(zt) : 0u);
+            ps[SL][c] = bload(rFS, oks ? vf[c] : kNone, oks ? pf(zs) : 0u);
             if constexpr (LF) {
                 const bool okl = intr && jo[c] == 0 && jn[c] >= 1 && s >= 0 && s < nz;
-                pl[SL][c] = FS[okl ? (int64_t)s * sz + off[c] : safe];
+                pl[SL][c] = bload(rFS, okl ? vf[c] : kNone, okl ? pf(s) : 0u);
             }
             if constexpr (G0) {
                 // level 0 at plane s+1 is the top (jo = 0) or the sub (jo = 1)
                 // of the old frontier, or the shell off the interior
                 const int zz = s + 1;
                 const bool ok0 = rt[c] >= 1 && zz >= -R && zz < nz + R;
-                const float* src = (rt[c] == 2 && jo[c] == 1 && zz >= 0 && zz < nz) ? FS : FT;
-                p0[SL][c] = src[ok0 ? (int64_t)zz * sz + off[c] : safe];
+                const bool sub = rt[c] == 2 && jo[c] == 1 && zz >= 0 && zz < nz;
+                p0[SL][c] = bload(sub ? rFS : rFT, ok0 ? vf[c] : kNone, ok0 ? pf(zz) : 0u);
+                if constexpr (LF) {
+                    const int zp = s - R;
+                    const bool okp = intr && jo[c] == 1 && jn[c] >= 2 && zp >= 0 && zp < nz;
+                    pp[SL][c] = bload(rFS, okp ? vf[c] : kNone, okp ? pf(zp) : 0u);
+                }
+            }
+            {
+                // the shell ring's input: needed on shell rows, on shell
+                // planes, and in tiles that reach the x boundary
+                const int zh = s + R;
+                const bool inz = zh >= 0 && zh < nz;
+                const bool okh = rt[c] != 0 && zh >= -R && zh < nz + R &&
+                                 (rt[c] == 1 || !inz || (xb && !xin[c]));
+                ph[SL][c] = bload(rFT, okh ? vf[c] : kNone, okh ? pf(zh) : 0u);
             }
             if constexpr (CRING) {
                 const bool okc = intr && own[c] && jn[c] > jo[c] && s >= 0 && s < nz &&
                                  s >= z0 - R * (L - 1) && s < z1 + R * (L - 1);
 #pragma unroll
                 for (int k = 0; k < KR; ++k)
-                    pc[SL][c][k] = load_coef(W, okc ? k * sk + (int64_t)s * sz + off[c] : safe);
+                    pc[SL][c][k] = cload(coef, crs(k), okc ? vc[c] : kNone, okc ? pc_(s) : 0u);
             }
         }
     };
@@ -201,7 +253,9 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         constexpr int SL = PD == 2 ? set : 0;      // prefetch slot holding step s
         constexpr bool XB = decltype(mode)::value == 1;
         constexpr bool FAST = decltype(mode)::value == 2;
-        float ft[CPT], fs[CPT], fl[CPT], f0n[CPT];
+        float ft[CPT], fs[CPT], fl[CPT], f0n[CPT], fp[CPT];
+        const int zh = s + R;
+        const bool inzh = zh >= 0 && zh < nz;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             ft[c] = pt[SL][c];
@@ -209,6 +263,11 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             fl[c] = LF ? pl[SL][c] : 0.0f;
             // G0: level 0 at plane s+1, staged at the end of this step
             f0n[c] = G0 ? p0[SL][c] : 0.0f;
+            fp[c] = (G0 && LF) ? pp[SL][c] : 0.0f;
+#pragma unroll
+            for (int i = NSH - 1; i > 0; --i) sh[c][i] = sh[c][i - 1];
+            // rows whose top is level 0 find it at plane s + R in ft
+            sh[c][0] = (rt[c] == 2 && jo[c] == 0 && inzh) ? ft[c] : ph[SL][c];
             if constexpr (CRING) {
 #pragma unroll
                 for (int i = NR - 1; i > 0; --i)
@@ -217,11 +276,6 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
 #pragma unroll
                 for (int k = 0; k < KR; ++k) cr[c][0][k] = pc[SL][c][k];
             }
-        }
-        if constexpr (PD == 2) {
-            if (s + 2 < s_end) prefetch(s + 2, ic<SL>{});
-        } else {
-            if (s + 1 < s_end) prefetch(s + 1, ic<0>{});
         }
         float vt[CPT], vs[CPT];
 #pragma unroll
@@ -233,16 +287,16 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             // active: no row computes it or reads it, so its values are unused
             const bool act = FAST || level_active(j, z);
             const bool zin = FAST || (z >= 0 && z < nz);
-            const int64_t zo = (int64_t)z * sz;
             const int jq = j >= 1 ? j - 1 : 0;
             const float* P = lds[set][jq];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
                 float v = 0.0f;
                 if (rt[c] != 0 && act) {
+                    const float shv = sh[c][j * R];
                     if (rt[c] == 1 || !zin) {
-                        // boundary shell (time independent): read from the frontier
-                        v = FT[zo + off[c]];
+                        // boundary shell (time independent)
+                        v = shv;
                     } else {
                         v = (j == jo[c]) ? ft[c] : ((j == jo[c] - 1) ? fs[c] : 0.0f);
                         if (j >= 1 && j > jo[c] && j <= jn[c]) {
@@ -253,8 +307,9 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
 #pragma unroll
                                     for (int k = 0; k < K; ++k) Wv[k] = cr[c][jq * R][k];
                                 } else {
+                                    const uint32_t so = pc_(z);
 #pragma unroll
-                                    for (int k = 0; k < K; ++k) Wv[k] = load_coef(W, k * sk + zo + off[c]);
+                                    for (int k = 0; k < K; ++k) Wv[k] = cload(coef, crs(k), vc[c], so);
                                 }
                             }
                             float pv = 0.0f;
@@ -262,16 +317,16 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                                 if (j == 1)
                                     pv = fl[c];
                                 else if (G0 && j == 2)
-                                    pv = (jo[c] == 0 ? FT : FS)[zo + off[c]];
+                                    pv = jo[c] == 0 ? sh[c][2 * R] : fp[c];
                                 else
                                     pv = qv[j >= 2 ? j - 2 : 0][c][0];
                             }
                             float zq[Q];
                             if (G0 && j == 1) {
-                                // level 0 (the old frontier top here: jo = 0) from
-                                // cache; planes off the interior are the shell
+                                // level 0 (the old frontier top here: jo = 0)
+                                // at planes z - R .. z + R, from the shell ring
 #pragma unroll
-                                for (int i = 0; i < Q; ++i) zq[i] = FT[(int64_t)(z - R + i) * sz + off[c]];
+                                for (int i = 0; i < Q; ++i) zq[i] = sh[c][2 * R - i];
                             } else {
 #pragma unroll
                                 for (int i = 0; i < Q; ++i) zq[i] = qv[jq][c][i];
@@ -295,8 +350,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                         }
                         if constexpr (XB) {
                             // columns outside [0, nx) hold the shell at every level
-                            const float sh = FT[zo + off[c]];
-                            v = xin[c] ? v : sh;
+                            v = xin[c] ? v : shv;
                         }
                     }
                 }
@@ -313,13 +367,12 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         // new frontier: the top two levels of the row, at their planes
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            if (rt[c] == 2 && own[c]) {
-                const int zt = s - (jn[c] - 1) * R, zs = s - (jn[c] - 2) * R;
-                if (outx[c]) {
-                    if (zt >= z0 && zt < z1) NT_[(int64_t)zt * sz + off[c]] = vt[c];
-                    if (zs >= z0 && zs < z1) NS[(int64_t)zs * sz + off[c]] = vs[c];
-                }
-            }
+            const bool row = rt[c] == 2 && own[c];
+            const int zt = s - (jn[c] - 1) * R, zs = s - (jn[c] - 2) * R;
+            const bool okt = row && zt >= z0 && zt < z1;
+            const bool oks = row && zs >= z0 && zs < z1;
+            bstore(rNT, vt[c], (okt && outx[c]) ? vf[c] : kNone, okt ? pf(zt) : 0u);
+            bstore(rNS, vs[c], (oks && outx[c]) ? vf[c] : kNone, oks ? pf(zs) : 0u);
         }
         // stage the planes read in-plane next step: level j-1 at plane
         // z_j(s+1), which is queue index R+1 of level j-1 now (R steps old)
@@ -329,6 +382,13 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             for (int c = 0; c < CPT; ++c)
                 if (wvu + NWV * c < NCOL)
                     lds[set ^ 1][j - 1][lidx[c]] = (G0 && j == 1) ? f0n[c] : qv[j - 1][c][R + 1];
+        // operands of a later step, issued after this step's work so that no
+        // wait inside it covers them
+        if constexpr (PD == 2) {
+            if (s + 2 < s_end) prefetch(s + 2, ic<SL>{});
+        } else {
+            if (s + 1 < s_end) prefetch(s + 1, ic<0>{});
+        }
         __syncthreads();
     };
 
@@ -374,9 +434,9 @@ hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
     wt.alpha = a.wt.alpha;
     hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD>), dim3(ntiles),
                        dim3(NWV * 64), 0, s, a.ftop_o, a.fsub_o, a.ftop_n, a.fsub_n,
-                       static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.sy,
-                       a.d.sz, a.d.org(), wt, (int)a.t0, (int)a.nt, a.first_centre, a.xo, a.gx,
-                       a.zchunk, a.gz, ntiles);
+                       static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.h, a.d.sy,
+                       a.d.sz, a.field_bytes, a.coef_bytes, wt, (int)a.t0, (int)a.nt,
+                       a.first_centre, a.xo, a.gx, a.zchunk, a.gz, ntiles);
     return hipGetLastError();
 }
 
