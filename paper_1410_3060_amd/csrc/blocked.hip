@@ -441,8 +441,9 @@ hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
 }
 
 // Workgroup shape per (kind, H): waves, 64-lane x chunks, coefficient ring,
-// level 0 from cache (G0), prefetch depth.  Register budget per column: L
-// z-queues of 2R+1 values, and with the ring (L-1)R+1 planes of K values.
+// level 0 from the shell ring (G0), prefetch depth.  Register budget per
+// column: L z-queues of 2R+1 values, the shell ring of LR+1 values, and with
+// the coefficient ring (L-1)R+1 planes of K values.
 template <int KIND, typename CT>
 hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
     constexpr int R = kind_traits<KIND>::R;
@@ -456,15 +457,17 @@ hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
         if (H == 4) return launch_cfg<KIND, CT, 4, 10, 1, true>(a, s);
         if (H == 6) return launch_cfg<KIND, CT, 6, 14, 1, true, false, 1>(a, s);
     } else if constexpr (KIND == 5) {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, true, true, 1>(a, s);
+        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, true, 1>(a, s);
+    } else if constexpr (KIND == 4) {
+        if (H == 2) return launch_cfg<KIND, CT, 2, 16, 1, false, true, 1>(a, s);
     } else {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 16, 2, false, true, 1>(a, s);
+        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, true, 2>(a, s);
     }
     return hipErrorInvalidValue;
 }
 
 // x chunks of the configuration above (host side)
-int cfg_xch(int kind, int H) { return ((kind == 2 && (H == 4 || H == 6)) || kind == 5) ? 1 : 2; }
+int cfg_xch(int kind, int H) { return ((kind == 2 && (H == 4 || H == 6)) || kind >= 3) ? 1 : 2; }
 
 }  // namespace
 
