@@ -19,11 +19,8 @@ namespace stn {
 
 namespace {
 
-constexpr int NT = 256;  // threads per workgroup
-constexpr int NW = NT / 64;
-
-template <int KIND, typename CT, int RPT>
-__global__ __launch_bounds__(NT) void naive_step_kernel(
+template <int KIND, typename CT, int RPT, int NW>
+__global__ __launch_bounds__(NW * 64) void naive_step_kernel(
     const float* __restrict__ cur, const float* prev, float* out, const CT* __restrict__ coef,
     int64_t sk, int nx, int ny, int nz, int64_t sy, int64_t sz, int64_t org, weights wt,
     int zchunk, int gx, int gy, int ntiles) {
@@ -174,9 +171,15 @@ __global__ __launch_bounds__(NT) void naive_step_kernel(
     }
 }
 
+// Rows per lane and waves per workgroup (tile 64 x NW*RPT), measured per kind:
+// the radius-4 kinds take 8 or 16 waves (taller tiles re-read fewer halo rows).
 template <int KIND>
 constexpr int naive_rpt() {
-    return kind_traits<KIND>::R == 1 ? 8 : 4;
+    return KIND == 1 || KIND == 2 ? 8 : (KIND == 4 ? 4 : 1);
+}
+template <int KIND>
+constexpr int naive_nw() {
+    return KIND == 1 || KIND == 2 ? 4 : (KIND == 4 ? 8 : 16);
 }
 
 template <int KIND, typename CT>
@@ -184,6 +187,7 @@ hipError_t launch_kind(const float* cur, const float* prev, float* out, const vo
                        int64_t sk, const dims& d, const host_weights& hw, int zchunk,
                        hipStream_t s) {
     constexpr int RPT = naive_rpt<KIND>();
+    constexpr int NW = naive_nw<KIND>();
     constexpr int TY = NW * RPT;
     const int gx = (d.nx + 63) / 64, gy = (d.ny + TY - 1) / TY;
     const int gz = (d.nz + zchunk - 1) / zchunk;
@@ -193,7 +197,8 @@ hipError_t launch_kind(const float* cur, const float* prev, float* out, const vo
     weights wt;
     for (int i = 0; i < 5; ++i) wt.w[i] = hw.w[i];
     wt.alpha = hw.alpha;
-    hipLaunchKernelGGL((naive_step_kernel<KIND, CT, RPT>), dim3((unsigned)ntiles), dim3(NT), 0, s,
+    hipLaunchKernelGGL((naive_step_kernel<KIND, CT, RPT, NW>), dim3((unsigned)ntiles), dim3(NW * 64),
+                       0, s,
                        cur, prev, out, static_cast<const CT*>(coef), sk, d.nx, d.ny, d.nz, d.sy,
                        d.sz, d.org(), wt, zchunk, gx, gy, (int)ntiles);
     return hipGetLastError();
@@ -274,20 +279,22 @@ int pick_zchunk(int nz, long long txy, long long slots, int R) {
     return best;
 }
 
-int naive_default_zchunk(int kind, const dims& d) {
-    const int R = (kind == 1 || kind == 2) ? 1 : 4;
-    const int RPT = R == 1 ? 8 : 4;
-    const int TY = NW * RPT;
+template <int KIND>
+int zchunk_for(const dims& d) {
+    constexpr int RPT = naive_rpt<KIND>(), NW = naive_nw<KIND>(), TY = NW * RPT;
     const long long txy = (long long)((d.nx + 63) / 64) * ((d.ny + TY - 1) / TY);
-    const void* k = nullptr;
+    const void* k = reinterpret_cast<const void*>(&naive_step_kernel<KIND, float, RPT, NW>);
+    return pick_zchunk(d.nz, txy, device_slots(k, NW * 64), kind_traits<KIND>::R);
+}
+
+int naive_default_zchunk(int kind, const dims& d) {
     switch (kind) {
-    case 1: k = reinterpret_cast<const void*>(&naive_step_kernel<1, float, 8>); break;
-    case 2: k = reinterpret_cast<const void*>(&naive_step_kernel<2, float, 8>); break;
-    case 3: k = reinterpret_cast<const void*>(&naive_step_kernel<3, float, 4>); break;
-    case 4: k = reinterpret_cast<const void*>(&naive_step_kernel<4, float, 4>); break;
-    default: k = reinterpret_cast<const void*>(&naive_step_kernel<5, float, 4>); break;
+    case 1: return zchunk_for<1>(d);
+    case 2: return zchunk_for<2>(d);
+    case 3: return zchunk_for<3>(d);
+    case 4: return zchunk_for<4>(d);
+    default: return zchunk_for<5>(d);
     }
-    return pick_zchunk(d.nz, txy, device_slots(k, NT), R);
 }
 
 hipError_t launch_naive_step(int kind, bool bf16, const float* cur, const float* prev, float* out,
