@@ -450,11 +450,15 @@ hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
     const int H = a.dw / (2 * R);
     if constexpr (KIND == 1) {
         if (H == 2) return launch_cfg<KIND, CT, 2, 6, 2>(a, s);
+        if (H == 3) return launch_cfg<KIND, CT, 3, 8, 2>(a, s);
         if (H == 4) return launch_cfg<KIND, CT, 4, 10, 2>(a, s);
+        if (H == 5) return launch_cfg<KIND, CT, 5, 12, 2>(a, s);
         if (H == 6) return launch_cfg<KIND, CT, 6, 14, 2>(a, s);
     } else if constexpr (KIND == 2) {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 6, 2, true>(a, s);
+        if (H == 2) return launch_cfg<KIND, CT, 2, 6, 1, true>(a, s);
+        if (H == 3) return launch_cfg<KIND, CT, 3, 8, 1, true, true, 2>(a, s);
         if (H == 4) return launch_cfg<KIND, CT, 4, 10, 1, true>(a, s);
+        if (H == 5) return launch_cfg<KIND, CT, 5, 12, 1, true, false, 1>(a, s);
         if (H == 6) return launch_cfg<KIND, CT, 6, 14, 1, true, false, 1>(a, s);
     } else if constexpr (KIND == 5) {
         if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, true, 1>(a, s);
@@ -467,7 +471,10 @@ hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
 }
 
 // x chunks of the configuration above (host side)
-int cfg_xch(int kind, int H) { return ((kind == 2 && (H == 4 || H == 6)) || kind >= 3) ? 1 : 2; }
+int cfg_xch(int kind, int H) {
+    (void)H;
+    return kind == 1 ? 2 : 1;
+}
 
 }  // namespace
 
@@ -475,10 +482,12 @@ bool blocked_supported(int kind, int dw) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;
     if (dw % (2 * R) != 0) return false;
     const int H = dw / (2 * R);
-    return R == 1 ? (H == 2 || H == 4 || H == 6) : (H == 2);
+    return R == 1 ? (H >= 2 && H <= 6) : (H == 2);
 }
 
-int blocked_default_dw(int kind) { return (kind == 1 || kind == 2) ? 8 : 16; }
+// measured on MI355X: 6 for the 7-point variable-coefficient stencil (512^3),
+// 4 for the constant one (64^3), the only width provided for radius 4
+int blocked_default_dw(int kind) { return kind == 1 ? 4 : (kind == 2 ? 6 : 16); }
 
 int blocked_max_xo(int kind, int dw) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;

@@ -48,7 +48,7 @@ def test_blocked_equals_naive_bitwise(index, nt):
 
 
 @pytest.mark.parametrize("index", [1, 3])
-@pytest.mark.parametrize("dw", [4, 12])
+@pytest.mark.parametrize("dw", [4, 6, 10, 12])
 def test_blocked_other_diamond_widths(index, dw):
     for nt in (5, 6, 13):
         wl = workloads.make(index, n=SIZES[index], nt=nt)
