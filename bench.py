@@ -41,7 +41,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scheme", choices=("blocked", "naive"), default="blocked",
                     help="scheme of the timed run (the other one is timed among the extras)")
-    ap.add_argument("--dw", type=int, default=16)
+    ap.add_argument("--workload", type=int, default=4, choices=(1, 2, 3, 4, 5),
+                    help="workload of the timed run (4: 25-point variable coefficients, 480^3)")
+    ap.add_argument("--dw", type=int, default=0, help="diamond width (0: the library's choice)")
     ap.add_argument("--no-extras", action="store_true", help="skip naive/BF16/adjoint legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
@@ -78,33 +80,44 @@ def main():
         return
 
     t_gen = time.time()
-    wl = workloads.make(4, n=args.n)
+    wl = workloads.make(args.workload, n=args.n)
     log(f"[bench] generated {wl.name} n={wl.n3} in {time.time() - t_gen:.1f}s")
-    h, nt = wl.halo, wl.nt
+    h, nt, kind = wl.halo, wl.nt, wl.kind
     nx, ny, nz = wl.n3
     lups = nx * ny * nz * nt
+    leapfrog = kind in (4, 5)
+    w = wl.w if kind == 1 else (st.L8_WEIGHTS if leapfrog else ())
+    dw = args.dw or st.default_dw(kind)
 
-    def upload_fields():
-        a = st.alloc_field(wl.n3, h)
-        a.copy_(torch.from_numpy(wl.u0))
-        b = st.alloc_field(wl.n3, h)
-        return a, b
+    def upload(a):
+        t = st.alloc_field(wl.n3, h)
+        t.copy_(torch.from_numpy(a))
+        return t
 
-    coef32 = st.alloc_field(wl.n3, h, count=13)
-    coef32.copy_(torch.from_numpy(wl.coef))
-    u_a, u_b = upload_fields()
-    u0_dev = u_a.clone()
+    def upload_coef(arr, dtype):
+        if arr is None:
+            return None
+        t = st.alloc_field(wl.n3, h, count=arr.shape[0], dtype=dtype)
+        src = torch.from_numpy(arr)
+        t.copy_(src.view(torch.bfloat16) if dtype == torch.bfloat16 else src)
+        return t
+
+    coef32 = upload_coef(wl.coef, torch.float32)
+    init_a = upload(wl.u_prev if leapfrog else wl.u0)
+    init_b = upload(wl.u0 if leapfrog else np.zeros_like(wl.u0))
+    u_a, u_b = st.field_like(init_a, h), st.field_like(init_b, h)
 
     def timed(ctx, coef, steps, warmup):
         """Run warmup + steps full runs; returns per-run seconds (HIP events on the stream)."""
         times = []
         for i in range(warmup + steps):
-            u_a.copy_(u0_dev)
+            u_a.copy_(init_a)
+            u_b.copy_(init_b)
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            ctx.run(st.KIND_25PT_VAR, u_a, u_b, nt, halo=h, coef=coef)
+            ctx.run(kind, u_a, u_b, nt, halo=h, coef=coef, w=w, alpha=wl.alpha)
             e1.record(stream)
             torch.cuda.synchronize()
             if i >= warmup:
@@ -113,17 +126,17 @@ def main():
 
     blocked = args.scheme == "blocked"
     if blocked:
-        n_launch = len(st.plan_rows(st.KIND_25PT_VAR, args.dw, ny, nt))
-        bpl = model.blocked_bytes_per_lup(st.KIND_25PT_VAR, args.dw)
-        kname = "blocked_row_kernel<3, float, H=%d>" % (args.dw // 8)
+        n_launch = len(st.plan_rows(kind, dw, ny, nt))
+        bpl = model.blocked_bytes_per_lup(kind, dw)
+        kname = "blocked_row_kernel<%d, float, H=%d>" % (kind, dw // (2 * model.RADIUS[kind]))
         tkey = "blocked_row_kernel"
     else:
         n_launch = nt
-        bpl = model.naive_code_balance(st.KIND_25PT_VAR)
-        kname = "naive_step_kernel<3, float, 4>"
+        bpl = model.naive_code_balance(kind)
+        kname = "naive_step_kernel<%d, float>" % kind
         tkey = "naive_step_kernel"
     log(f"[bench] {args.scheme}: {n_launch} kernel launches per run")
-    ctx_b = st.Context(st.BLOCKED, dw=args.dw, stream=stream)
+    ctx_b = st.Context(st.BLOCKED, dw=dw, stream=stream)
     ctx_n = st.Context(st.NAIVE, stream=stream)
     tb = timed(ctx_b if blocked else ctx_n, coef32, args.steps, args.warmup)
     t_step = float(np.median(tb))
@@ -134,7 +147,7 @@ def main():
     # (launch gaps and the few small copies of a run included)
     avg_launch = t_step / n_launch
     achieved = bpl * lups / n_launch / avg_launch / 1e9
-    traffic = measured_traffic(tkey, wl.name, args.dw if blocked else 0)
+    traffic = measured_traffic(tkey, wl.name, dw if blocked else 0)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 3),
@@ -148,25 +161,25 @@ def main():
         other = max(2, args.steps // 2)
         tn_s = t_step if not blocked else float(np.median(timed(ctx_n, coef32, other, 1)))
         tb_s = t_step if blocked else float(np.median(timed(ctx_b, coef32, other, 1)))
-        for name, t, b in (("naive", tn_s, model.naive_code_balance(st.KIND_25PT_VAR)),
-                           ("blocked", tb_s, model.blocked_bytes_per_lup(st.KIND_25PT_VAR, args.dw))):
+        for name, t, b in (("naive", tn_s, model.naive_code_balance(kind)),
+                           ("blocked", tb_s, model.blocked_bytes_per_lup(kind, dw))):
             extras[name] = {"glups": round(lups / t / 1e9, 2), "ms_per_run": round(t * 1e3, 3),
                             "bytes_per_lup": round(b, 3),
                             "algorithmic_GBps": round(b * lups / t / 1e9, 1)}
         extras["blocked_over_naive"] = round(tn_s / tb_s, 3)
         log(f"[bench] naive {extras['naive']['glups']}, blocked {extras['blocked']['glups']} GLUP/s")
-        # BF16 coefficient storage
-        bits = workloads.to_bf16_bits(wl.coef)
-        coef16 = st.alloc_field(wl.n3, h, count=13, dtype=torch.bfloat16)
-        coef16.copy_(torch.from_numpy(bits.view(np.int16)).view(torch.bfloat16))
-        del bits
-        tb16 = float(np.median(timed(ctx_b, coef16, max(2, args.steps // 2), 1)))
-        tn16 = float(np.median(timed(ctx_n, coef16, max(2, args.steps // 2), 1)))
-        extras["bf16"] = {"blocked_glups": round(lups / tb16 / 1e9, 2),
-                          "naive_glups": round(lups / tn16 / 1e9, 2),
-                          "blocked_over_naive": round(tn16 / tb16, 3)}
-        log(f"[bench] bf16: blocked {lups / tb16 / 1e9:.1f}, naive {lups / tn16 / 1e9:.1f} GLUP/s")
-        del coef16
+        if wl.coef is not None:
+            # BF16 coefficient storage
+            coef16 = upload_coef(workloads.to_bf16_bits(wl.coef).view(np.int16), torch.bfloat16)
+            tb16 = float(np.median(timed(ctx_b, coef16, other, 1)))
+            tn16 = float(np.median(timed(ctx_n, coef16, other, 1)))
+            extras["bf16"] = {"blocked_glups": round(lups / tb16 / 1e9, 2),
+                              "naive_glups": round(lups / tn16 / 1e9, 2),
+                              "blocked_over_naive": round(tn16 / tb16, 3)}
+            log(f"[bench] bf16: blocked {lups / tb16 / 1e9:.1f}, naive {lups / tn16 / 1e9:.1f} GLUP/s")
+            del coef16
+        if args.workload != 3 and args.n is None:
+            extras["7pt_var"] = scheme_leg(st, workloads, model, torch, np, stream, 3)
         try:
             extras["adjoint"] = adjoint_leg(st, workloads, torch, np, stream, args)
         except Exception as e:  # the adjoint leg reports, it does not sink the line
@@ -179,7 +192,7 @@ def main():
         cpu = cpu_leg(wl, args.cpu_seconds)
 
     line = {
-        "metric": "GLUP/s (25pt var-coef 480^3, 100 steps) + HBM GB/s; blocked vs naive",
+        "metric": "GLUP/s (%s) + HBM GB/s; blocked vs naive" % wl.name,
         "value": round(value, 2),
         "unit": "GLUP/s",
         "n_gpus": 1,
@@ -191,9 +204,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "kind": "25pt-var", "n": list(wl.n3), "halo": h, "nt": nt,
-                   "scheme": args.scheme, "dw": args.dw if blocked else None, "coef_dtype": "f32",
-                   "seed": [workloads.SEED_BASE, 4]},
+        "config": {"workload": wl.name, "kind": kind, "n": list(wl.n3), "halo": h, "nt": nt,
+                   "scheme": args.scheme, "dw": dw if blocked else None, "coef_dtype": "f32",
+                   "seed": [workloads.SEED_BASE, args.workload]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extras": extras,
@@ -208,15 +221,14 @@ def measured_traffic(key, workload, dw):
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
-        rec = json.load(open(path))[key]
+        rec = json.load(open(path))[f"{key}@{workload}"]
     except (OSError, KeyError, ValueError):
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != rec.get("source_sha256") or rec.get("workload") != workload or \
-            rec.get("dw", 0) != dw:
+    if h.hexdigest() != rec.get("source_sha256") or rec.get("dw", 0) != dw:
         return None
     return float(rec["hbm_bytes_per_launch"])
 
@@ -241,6 +253,42 @@ def copy_probe(torch, nbytes=1 << 32, reps=10):
     del a, b
     return {"bytes_per_copy": 2 * nbytes, "GBps": round(2 * nbytes / sec / 1e9, 1),
             "ms": round(sec * 1e3, 3)}
+
+
+def scheme_leg(st, workloads, model, torch, np, stream, index, reps=3):
+    """Naive and blocked GLUP/s of another workload (default diamond width)."""
+    wl = workloads.make(index)
+    h, kind = wl.halo, wl.kind
+    a0 = st.alloc_field(wl.n3, h)
+    a0.copy_(torch.from_numpy(wl.u0))
+    b0 = st.alloc_field(wl.n3, h)
+    cf = st.alloc_field(wl.n3, h, count=wl.coef.shape[0])
+    cf.copy_(torch.from_numpy(wl.coef))
+    a, b = st.field_like(a0, h), st.field_like(b0, h)
+    dw = st.default_dw(kind)
+    out = {"workload": wl.name, "dw": dw}
+    for scheme, name in ((st.NAIVE, "naive"), (st.BLOCKED, "blocked")):
+        ctx = st.Context(scheme, stream=stream)
+        ts = []
+        for i in range(reps + 1):
+            a.copy_(a0)
+            b.copy_(b0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.run(kind, a, b, wl.nt, halo=h, coef=cf)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if i:
+                ts.append(e0.elapsed_time(e1) / 1e3)
+        ctx.close()
+        t = float(np.median(ts))
+        bpl = model.naive_code_balance(kind) if scheme == st.NAIVE else \
+            model.blocked_bytes_per_lup(kind, dw)
+        out[name] = {"glups": round(wl.lups / t / 1e9, 2), "bytes_per_lup": round(bpl, 3),
+                     "algorithmic_GBps": round(bpl * wl.lups / t / 1e9, 1)}
+    out["blocked_over_naive"] = round(out["blocked"]["glups"] / out["naive"]["glups"], 3)
+    return out
 
 
 def adjoint_leg(st, workloads, torch, np, stream, args):

@@ -171,6 +171,11 @@ const char* stencil_last_error(void);
 int stencil_plan_rows(stencil_kind kind, int32_t dw, int32_t ny, int64_t nt, int64_t* out,
                       int32_t cap);
 
+/* The diamond width the blocked scheme uses for `kind` when stencil_tuning.dw
+   is 0 (Sect. 4.2: a multiple of 2R, at least 4R), or 0 for an unknown kind.
+   No HIP call. */
+int32_t stencil_default_dw(stencil_kind kind);
+
 #ifdef __cplusplus
 }
 #endif

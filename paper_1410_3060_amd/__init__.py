@@ -68,7 +68,7 @@ class _Tuning(ctypes.Structure):
 
 
 EXPORTS = ("stencil_create", "stencil_run", "stencil_adjoint", "stencil_sync",
-           "stencil_destroy", "stencil_last_error", "stencil_plan_rows")
+           "stencil_destroy", "stencil_last_error", "stencil_plan_rows", "stencil_default_dw")
 
 _lib = None
 
@@ -99,6 +99,8 @@ def load(path: Optional[str] = None):
     lib.stencil_last_error.restype = ctypes.c_char_p
     lib.stencil_plan_rows.argtypes = [ctypes.c_int, i32, i32, i64, ctypes.POINTER(i64), i32]
     lib.stencil_plan_rows.restype = ctypes.c_int
+    lib.stencil_default_dw.argtypes = [ctypes.c_int]
+    lib.stencil_default_dw.restype = ctypes.c_int32
     if path is None:
         _lib = lib
     return lib
@@ -221,6 +223,14 @@ class Context:
 
     def sync(self):
         _check(load().stencil_sync(self._h))
+
+
+def default_dw(kind: int) -> int:
+    """Diamond width the blocked scheme uses for `kind` when none is given."""
+    dw = load().stencil_default_dw(kind)
+    if dw <= 0:
+        raise ValueError(f"unknown stencil kind {kind}")
+    return dw
 
 
 def plan_rows(kind: int, dw: int, ny: int, nt: int):

@@ -657,6 +657,15 @@ void stencil_destroy(stencil_ctx* ctx) {
     delete ctx;
 }
 
+int32_t stencil_default_dw(stencil_kind kind) {
+    const int k = (int)kind;
+    if (k < 1 || k > 5) {
+        fail(STENCIL_ERR_INVALID, "unknown stencil kind %d", k);
+        return 0;
+    }
+    return stn::blocked_default_dw(k);
+}
+
 int stencil_plan_rows(stencil_kind kind, int32_t dw, int32_t ny, int64_t nt, int64_t* out,
                       int32_t cap) {
     const int k = (int)kind;

@@ -27,6 +27,15 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
+def test_default_diamond_widths():
+    assert [st.default_dw(k) for k in (1, 2, 3, 4, 5)] == [4, 6, 16, 16, 16]
+    assert st.load().stencil_default_dw(9) == 0
+    for k in (1, 2, 3, 4, 5):
+        R = 1 if k <= 2 else 4
+        dw = st.default_dw(k)
+        assert dw % (2 * R) == 0 and dw >= 4 * R
+
+
 def test_struct_layouts_match_header():
     # sizes of the C structs as laid out by the x86-64 SysV ABI
     assert ctypes.sizeof(st._Grid) == 48
