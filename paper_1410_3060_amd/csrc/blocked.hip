@@ -22,9 +22,10 @@
 // depends on y -- where the row sits in the diamond, which levels it reads
 // from the old frontier and which it computes -- is uniform across the wave
 // and decided with scalar branches.  Per step a row reads from memory only
-// the two old-frontier levels below the diamond (prefetched ahead) and, for
-// kinds 2 and 5, one plane of coefficients into a register ring that serves
-// every level (a coefficient is read once per diamond).  Levels are computed
+// the two old-frontier levels below the diamond and a shell value (prefetched
+// ahead) and, where the registers allow (CRING), one plane of coefficients
+// into a register ring that serves every level (a coefficient is then read
+// once per diamond; otherwise once per level).  Levels are computed
 // across the whole tile width; values near the x edges that depend on columns
 // outside the tile are wrong but never stored and never read by a stored
 // value (the overlapped-halo argument: level j is correct R*j columns inside
