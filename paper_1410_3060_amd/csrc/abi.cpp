@@ -250,6 +250,21 @@ int ensure_frontier(stencil_ctx* ctx, size_t bytes) {
     return STENCIL_OK;
 }
 
+// Limits of the blocked scheme, checked with the other arguments before any
+// HIP call: a provided diamond width, and 32-bit byte offsets (fields below
+// 2 GiB from their padded origin).
+int check_blocked(const stencil_ctx* ctx, int kind, const stencil_grid* g) {
+    const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
+    if (!stn::blocked_supported(kind, dw))
+        return fail(STENCIL_ERR_UNSUPPORTED, "blocked scheme: dw=%d is not provided for kind %d", dw,
+                    kind);
+    const size_t fbytes = (size_t)field_span(g) * sizeof(float);
+    if (fbytes >= ((size_t)1 << 31))
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "blocked scheme: a field spans %zu bytes, the limit is 2 GiB", fbytes);
+    return STENCIL_OK;
+}
+
 // Blocked time loop (diamond rows of plan.h, one launch per row).  The
 // frontier pair alternates between the caller's buffers and a workspace pair;
 // when the number of rows is odd the initial state is first copied to the
@@ -259,23 +274,12 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
                 int64_t nt) {
     const int R = kind_radius(kind);
     const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
-    if (!stn::blocked_supported(kind, dw))
-        return fail(STENCIL_ERR_UNSUPPORTED, "blocked scheme: dw=%d is not provided for kind %d", dw,
-                    kind);
     const int H = dw / (2 * R);
     const int L = 2 * H - 1;
-    // the kernel addresses a tile's columns with 32-bit offsets
-    if ((int64_t)(dw + 2 * R) * g->sy + 256 > INT32_MAX)
-        return fail(STENCIL_ERR_UNSUPPORTED, "blocked scheme: row stride sy=%lld too large",
-                    (long long)g->sy);
     const stn::dims d = to_dims(g);
     const stn::diamond_plan plan = stn::make_plan(R, dw, g->ny, nt);
     const field_layout FL = layout_of(g);
     const size_t fbytes = FL.span * sizeof(float);
-    // the kernel addresses fields with 32-bit byte offsets below 2^31
-    if (fbytes >= ((size_t)1 << 31))
-        return fail(STENCIL_ERR_UNSUPPORTED,
-                    "blocked scheme: a field spans %zu bytes, the limit is 2 GiB", fbytes);
     int rc = ensure_frontier(ctx, FL.bytes(2));
     if (rc) return rc;
     float* w0 = FL.at(ctx->frontier, 0);
@@ -605,6 +609,10 @@ int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
         if (result_slot) *result_slot = slot;
         return STENCIL_OK;
     }
+    if (ctx->scheme == STENCIL_BLOCKED) {
+        rc = check_blocked(ctx, k, grid);
+        if (rc) return rc;
+    }
     rc = set_device(ctx);
     if (rc) return rc;
     if (ctx->tuning.ckpt_every > 0) {
@@ -633,6 +641,11 @@ int stencil_adjoint(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* gri
     if (!seed || !grad_u0 || !grad_um1 || !grad_c)
         return fail(STENCIL_ERR_INVALID, "adjoint field pointer is NULL");
     if (empty(grid)) return STENCIL_OK;
+    if (ctx->scheme == STENCIL_BLOCKED) {
+        // a missing recording is rebuilt with the context's (blocked) forward
+        rc = check_blocked(ctx, 5, grid);
+        if (rc) return rc;
+    }
     rc = set_device(ctx);
     if (rc) return rc;
     return run_adjoint(ctx, grid, coeffs, nt, seed, grad_u0, grad_um1, grad_c);

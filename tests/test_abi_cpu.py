@@ -147,6 +147,19 @@ def test_blocked_dw_must_fit_radius():
     st.load().stencil_destroy(h)
 
 
+def test_blocked_limits_are_checked_before_any_device_call():
+    # a dw the library does not provide, and fields above 2 GiB (32-bit
+    # offsets), are rejected with the other arguments, before any HIP call
+    rc, h = make_ctx(scheme=st.BLOCKED, dw=14)
+    g = grid(halo=1)
+    assert run(h, 2, g, coeffs(2, g))[0] == 2 and "dw=14" in msg()
+    st.load().stencil_destroy(h)
+    rc, h = make_ctx(scheme=st.BLOCKED)
+    g = grid(nx=820, ny=820, nz=820, halo=4)
+    assert run(h, 3, g, coeffs(3, g))[0] == 2 and "2 GiB" in msg()
+    st.load().stencil_destroy(h)
+
+
 def test_adjoint_argument_errors():
     lib = st.load()
     rc, h = make_ctx()
