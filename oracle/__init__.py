@@ -65,6 +65,9 @@ def _load():
     lib.oracle_adjoint_wave_varc.argtypes = [i64, i64, i64, i64, D, D, D, D, i64, D,
                                              D, D, D, ctypes.c_int]
     lib.oracle_adjoint_wave_varc.restype = ctypes.c_int
+    lib.oracle_adjoint_jacobi_var.argtypes = [ctypes.c_int, i64, i64, i64, i64, D, D, i64, D,
+                                              D, D, ctypes.c_int]
+    lib.oracle_adjoint_jacobi_var.restype = ctypes.c_int
     lib.oracle_step_points.argtypes = [ctypes.c_int, i64, i64, i64, i64, D, D, D, D,
                                        ctypes.c_double, i64, ctypes.POINTER(i64), D]
     lib.oracle_step_points.restype = ctypes.c_int
@@ -178,6 +181,24 @@ def adjoint_wave_varc(um1, u0, c, h, nt, seed, w, nthreads=0):
     if rc != 0:
         raise ValueError("oracle_adjoint_wave_varc rejected its arguments")
     return g_um1, g_u0, g_c
+
+
+def adjoint_jacobi_var(kind, u0, coef, h, nt, seed, nthreads=0):
+    """Gradients (dJ/du_0, dJ/dW) of a loss with dJ/du_nt = seed for the
+    variable-coefficient kinds 2 (Fig. 1c) and 3 (Fig. 1d); dJ/dW has the
+    shape of coef (K arrays)."""
+    lib = _load()
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    cf = np.ascontiguousarray(coef, dtype=np.float64)
+    sd = np.ascontiguousarray(seed, dtype=np.float64)
+    nx, ny, nz = _dims(u0, h)
+    g_u0 = np.zeros_like(u0)
+    g_c = np.zeros_like(cf)
+    rc = lib.oracle_adjoint_jacobi_var(int(kind), nx, ny, nz, h, _p(u0), _p(cf), int(nt), _p(sd),
+                                       _p(g_u0), _p(g_c), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_adjoint_jacobi_var rejected its arguments")
+    return g_u0, g_c
 
 
 def interior(a, h):

@@ -309,6 +309,109 @@ int oracle_adjoint_wave_varc(int64_t nx, int64_t ny, int64_t nz, int64_t h,
 }
 
 /*
+ * Adjoint of the first-order variable-coefficient kinds 2 and 3 (Fig. 1c,
+ * 1d).  Not in the paper: with A the sweep operator of Fig. 1c/1d for fixed
+ * coefficients (zero Dirichlet boundary), u_{t+1} = A u_t, and a loss J with
+ * dJ/du_nt = seed, the adjoint fields are lambda_nt = seed,
+ * lambda_t = A^T lambda_{t+1}, and dJ/du_0 = lambda_0.  Written as a gather,
+ * A^T lambda at interior q sums, over the taps of the stencil, the weight a
+ * point p = q - offset gives u(q), times lambda(p), for interior p only:
+ *   kind 2:  (A^T l)(q) = sum_k W_k(q - o_k) l(q - o_k),  o_k = 0, -x, +x, -y, +y, -z, +z
+ *   kind 3:  (A^T l)(q) = W_0(q) l(q) + sum_{r,a} [ W_{ra}(q + r e_a) l(q + r e_a)
+ *                                                + W_{ra}(q - r e_a) l(q - r e_a) ]
+ * The coefficient gradients are dJ/dW_k(p) = sum_t lambda_{t+1}(p) * (the
+ * value W_k multiplies at p in step t): u_t(p + o_k) for kind 2, u_t(p) for
+ * W_0 and the pair u_t(p - r e_a) + u_t(p + r e_a) for W_{ra} of kind 3.
+ * g_coef holds K arrays of the box size (same layout as coef).  All levels of
+ * the forward run are kept (small grids only).
+ */
+static int inside(const box* b, int64_t x, int64_t y, int64_t z) {
+    return x >= 0 && y >= 0 && z >= 0 && x < b->nx && y < b->ny && z < b->nz;
+}
+
+int oracle_adjoint_jacobi_var(int kind, int64_t nx, int64_t ny, int64_t nz, int64_t h,
+                              const double* u0, const double* coef, int64_t nt,
+                              const double* seed, double* g_u0, double* g_coef, int nthreads) {
+    if ((kind != OK_7V && kind != OK_25V) || nx < 0 || ny < 0 || nz < 0 || nt < 0) return -1;
+    if (h < radius_of(kind) || !u0 || !coef || !seed || !g_u0 || !g_coef) return -1;
+    set_threads(nthreads);
+    box b = mkbox(nx, ny, nz, h);
+    const int64_t n = box_size(&b);
+    const int K = ncoef_of(kind);
+    double* hist = (double*)malloc((size_t)(nt > 0 ? nt : 1) * (size_t)n * sizeof(double));
+    double* la = (double*)calloc((size_t)n, sizeof(double));
+    double* ln = (double*)calloc((size_t)n, sizeof(double));
+    if (!hist || !la || !ln) { free(hist); free(la); free(ln); return -1; }
+    /* forward: hist slot t holds u_t, t = 0 .. nt-1 (shell included) */
+    if (nt >= 1) memcpy(hist, u0, (size_t)n * sizeof(double));
+    for (int64_t t = 1; t < nt; ++t) {
+        memcpy(hist + t * n, hist + (t - 1) * n, (size_t)n * sizeof(double)); /* the shell */
+        sweep_jacobi(kind, &b, hist + (t - 1) * n, hist + t * n, coef, NULL);
+    }
+    memset(g_coef, 0, (size_t)K * (size_t)n * sizeof(double));
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) la[at(&b, x, y, z)] = seed[at(&b, x, y, z)];
+    static const int ox[7] = {0, -1, 1, 0, 0, 0, 0};
+    static const int oy[7] = {0, 0, 0, -1, 1, 0, 0};
+    static const int oz[7] = {0, 0, 0, 0, 0, -1, 1};
+    const double* W = coef;
+    for (int64_t t = nt - 1; t >= 0; --t) {
+        const double* u = hist + t * n; /* u_t; la = lambda_{t+1} */
+#pragma omp parallel for schedule(static)
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    const int64_t q = at(&b, x, y, z);
+                    /* gradient terms of step t at p = q */
+                    if (kind == OK_7V) {
+                        for (int k = 0; k < 7; ++k)
+                            g_coef[k * n + q] += la[q] * u[at(&b, x + ox[k], y + oy[k], z + oz[k])];
+                    } else {
+                        g_coef[q] += la[q] * u[q];
+                        for (int r = 1; r <= 4; ++r) {
+                            const int64_t kx = 3 * (r - 1) + 1;
+                            g_coef[kx * n + q] += la[q] * (u[at(&b, x - r, y, z)] + u[at(&b, x + r, y, z)]);
+                            g_coef[(kx + 1) * n + q] += la[q] * (u[at(&b, x, y - r, z)] + u[at(&b, x, y + r, z)]);
+                            g_coef[(kx + 2) * n + q] += la[q] * (u[at(&b, x, y, z - r)] + u[at(&b, x, y, z + r)]);
+                        }
+                    }
+                    /* lambda_t(q) = (A^T lambda_{t+1})(q) */
+                    double v = 0.0;
+                    if (kind == OK_7V) {
+                        for (int k = 0; k < 7; ++k) {
+                            const int64_t px = x - ox[k], py = y - oy[k], pz = z - oz[k];
+                            if (inside(&b, px, py, pz)) {
+                                const int64_t pp = at(&b, px, py, pz);
+                                v += W[k * n + pp] * la[pp];
+                            }
+                        }
+                    } else {
+                        v = W[q] * la[q];
+                        for (int r = 1; r <= 4; ++r) {
+                            const int64_t kx = 3 * (r - 1) + 1;
+                            const int64_t nb[6][3] = {{x + r, y, z}, {x - r, y, z}, {x, y + r, z},
+                                                      {x, y - r, z}, {x, y, z + r}, {x, y, z - r}};
+                            for (int i = 0; i < 6; ++i) {
+                                if (!inside(&b, nb[i][0], nb[i][1], nb[i][2])) continue;
+                                const int64_t pp = at(&b, nb[i][0], nb[i][1], nb[i][2]);
+                                v += W[(kx + i / 2) * n + pp] * la[pp];
+                            }
+                        }
+                    }
+                    ln[q] = v;
+                }
+        double* tmp = la; la = ln; ln = tmp;
+    }
+    memset(g_u0, 0, (size_t)n * sizeof(double));
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) g_u0[at(&b, x, y, z)] = la[at(&b, x, y, z)];
+    free(hist); free(la); free(ln);
+    return 0;
+}
+
+/*
  * One update (Fig. 1b-1e) evaluated at a list of interior points, for
  * checking single sweeps of very large grids on sampled outputs.  pts holds
  * npts triples (x, y, z); out[i] receives the new value at point i (for the
