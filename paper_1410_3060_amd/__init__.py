@@ -221,6 +221,26 @@ class Context:
                                       int(nt), _ptr(seed), _ptr(grad_u0), _ptr(grad_um1),
                                       _ptr(grad_c)))
 
+    def adjoint_jacobi(self, kind: int, u0, u1, nt: int, *, halo: int, coef, seed, grad_u0,
+                       grad_c):
+        """Reverse time stepping of the Jacobi kinds 2 and 3; see stencil_adjoint
+        in include/stencil.h.  (u0, u1) is the forward's grid (u0 holds level 0
+        unless this context recorded the forward); grad_c is a float64
+        (K, z, y, x) tensor with the coefficients' element strides."""
+        import torch
+        if kind not in (KIND_7PT_VAR, KIND_25PT_VAR):
+            raise ValueError("adjoint_jacobi takes kinds 2 and 3")
+        g = grid_struct(u0, u1, halo)
+        c = coeff_struct(kind, u0, coef, (), 0.0)
+        for t in (seed, grad_u0):
+            if t.dtype != torch.float32 or _strides3(t) != _strides3(u0) or t.shape != u0.shape:
+                raise ValueError("adjoint fields must match the grid")
+        if (grad_c.dtype != torch.float64 or grad_c.shape != coef.shape or
+                grad_c.stride() != coef.stride()):
+            raise ValueError("grad_c must be float64 with the coefficients' shape and strides")
+        _check(load().stencil_adjoint(self._h, kind, ctypes.byref(g), ctypes.byref(c), int(nt),
+                                      _ptr(seed), _ptr(grad_u0), None, _ptr(grad_c)))
+
     def sync(self):
         _check(load().stencil_sync(self._h))
 

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libstencil.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("STENCIL_ARCH", "gfx950")
 
-SOURCES = ["naive.hip", "blocked.hip", "adjoint.hip", "abi.cpp"]
+SOURCES = ["naive.hip", "blocked.hip", "adjoint.hip", "adjoint_jacobi.hip", "abi.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

@@ -60,15 +60,17 @@ struct stencil_ctx {
     // blocked scheme frontier buffers (two pairs of fields)
     void* frontier = nullptr;
     size_t frontier_bytes = 0;
-    // checkpoints recorded by stencil_run for stencil_adjoint (kind 5)
+    // checkpoints recorded by stencil_run for stencil_adjoint (kinds 2, 3, 5)
     struct recording {
         bool valid = false;
+        int kind = 0;
         int nx = 0, ny = 0, nz = 0, halo = 0;
-        int64_t sy = 0, sz = 0, nt = 0;
+        int64_t sy = 0, sz = 0, nt = 0, sk = 0;
         int every = 0;            // checkpoint interval k
         const void* coef = nullptr;
         int dtype = 0;
-        void* buf = nullptr;      // 2 * n fields: (u_{qk-1}, u_{qk}) for q = 0 .. n-1
+        void* buf = nullptr;      // kind 5: 2n fields (u_{qk-1}, u_{qk}); kinds 2, 3: n
+                                  // fields u_{qk}; q = 0 .. n-1
         size_t bytes = 0;         // allocated size of buf
         size_t lead = 0, stride = 0;  // placement of the fields (elements)
         int n = 0;
@@ -358,16 +360,20 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
     return STENCIL_OK;
 }
 
-// Forward run in segments of k steps, copying (u_{t-1}, u_t) into checkpoint q
-// before segment q (t = q k).  A segment runs on a grid whose u[0], u[1] are
-// the buffers holding u_{t-1}, u_t, so the two-buffer convention (and with it
-// the boundary shell read at each level) is the same as in one long run.
+// Forward run in segments of k steps, copying the state at t = q k into
+// checkpoint q before segment q: (u_{t-1}, u_t) for the leapfrog, u_t for the
+// Jacobi kinds.  A segment runs on a grid whose u[0], u[1] are the buffers
+// holding (u_{t-1}, u_t) (leapfrog) or (u_t, the other buffer) (Jacobi), so
+// the two-buffer convention is the same as in one long run.  Jacobi
+// checkpoints get the boundary shell of u[0], the level-0 buffer.
 int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
                  int64_t nt, int k, stencil_ctx::recording* rec) {
     const field_layout FL = layout_of(g);
     const size_t span = FL.span;
+    const bool lf = kind_leapfrog(kind);
+    const size_t nf = lf ? 2 : 1;
     const int n = (int)((nt + k - 1) / k);
-    const size_t need = FL.bytes(2 * (size_t)n);
+    const size_t need = FL.bytes(nf * (size_t)n);
     if (!rec->buf || rec->bytes < need) {
         if (rec->buf) ws_free(ctx, rec->buf);
         rec->buf = nullptr;
@@ -387,19 +393,25 @@ int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stenci
         const int64_t t = (int64_t)q * k;
         const int64_t steps = std::min<int64_t>(k, nt - t);
         stencil_grid sub = *g;
-        sub.u[0] = g->u[t % 2];        // holds u_{t-1}
-        sub.u[1] = g->u[(t + 1) % 2];  // holds u_t
-        hipError_t e = hipMemcpyAsync(FL.at(rec->buf, 2 * (size_t)q), sub.u[0],
+        sub.u[0] = g->u[t % 2];        // leapfrog: u_{t-1}; Jacobi: u_t
+        sub.u[1] = g->u[(t + 1) % 2];  // leapfrog: u_t
+        hipError_t e = hipMemcpyAsync(FL.at(rec->buf, nf * (size_t)q), sub.u[0],
                                       span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
-        if (e == hipSuccess)
+        if (e == hipSuccess && lf)
             e = hipMemcpyAsync(FL.at(rec->buf, 2 * (size_t)q + 1), sub.u[1],
                                span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess && !lf && t % 2 == 1)
+            e = stn::launch_copy_shell(FL.at(rec->buf, (size_t)q),
+                                       static_cast<const float*>(g->u[0]), to_dims(g),
+                                       kind_radius(kind), ctx->stream);
         if (e != hipSuccess) return dev_fail(e, "checkpoint copy");
         const int rc = ctx->scheme == STENCIL_NAIVE ? run_naive(ctx, kind, &sub, c, steps)
                                                     : run_blocked(ctx, kind, &sub, c, steps);
         if (rc) return rc;
     }
     rec->valid = true;
+    rec->kind = kind;
+    rec->sk = c->sk;
     rec->nx = g->nx; rec->ny = g->ny; rec->nz = g->nz; rec->halo = g->halo;
     rec->sy = g->sy; rec->sz = g->sz; rec->nt = nt; rec->every = k;
     rec->coef = c->arrays;
@@ -407,9 +419,9 @@ int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stenci
     return STENCIL_OK;
 }
 
-bool recording_matches(const stencil_ctx::recording& r, const stencil_grid* g,
+bool recording_matches(const stencil_ctx::recording& r, int kind, const stencil_grid* g,
                        const stencil_coeffs* c, int64_t nt) {
-    return r.valid && r.nx == g->nx && r.ny == g->ny && r.nz == g->nz && r.halo == g->halo &&
+    return r.valid && r.kind == kind && r.sk == c->sk && r.nx == g->nx && r.ny == g->ny && r.nz == g->nz && r.halo == g->halo &&
            r.sy == g->sy && r.sz == g->sz && r.nt == nt && r.coef == c->arrays &&
            r.dtype == (int)c->dtype;
 }
@@ -439,7 +451,7 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
     const field_layout FL = layout_of(g);
     const size_t span = FL.span;
     int rc;
-    if (!recording_matches(rec, g, c, nt)) {
+    if (!recording_matches(rec, 5, g, c, nt)) {
         // no usable recording: rerun the forward from the initial state held by
         // the caller's buffers, on workspace copies
         void* p = nullptr;
@@ -560,6 +572,122 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
     return done(e, "adjoint");
 }
 
+// Reverse time stepping of the Jacobi kinds 2 and 3 (lambda_t = A^T
+// lambda_{t+1}, lambda_nt = seed) from the recorded checkpoints u_{qk}:
+// segments in reverse order; each recomputes u_{a+1} .. u_{b-1} from its
+// checkpoint with the naive step (bit-identical to the forward), runs the
+// reverse steps b-1 .. a into a ring of k + 1 lambda fields, and then adds
+// the gradient terms of the segment's steps in groups of up to
+// stn::grad_group_max(kind) steps per pass over the FP64 arrays.
+int run_adjoint_jacobi(stencil_ctx* ctx, int kind, const stencil_grid* g,
+                       const stencil_coeffs* c, int64_t nt, const float* seed, float* g_u0,
+                       double* g_c) {
+    const stn::dims d = to_dims(g);
+    const hipStream_t st = ctx->stream;
+    const bool bf16 = c->dtype == STENCIL_BF16;
+    const int K = kind_ncoef(kind);
+    hipError_t e = stn::launch_scale_copy(g_u0, seed, 1.0f, d, st);
+    for (int k = 0; k < K && e == hipSuccess; ++k) e = stn::launch_zero_f64(g_c + k * c->sk, d, st);
+    if (e != hipSuccess) return dev_fail(e, "adjoint setup");
+    if (nt == 0) return STENCIL_OK;
+    stencil_ctx::recording& rec = ctx->rec;
+    const field_layout FL = layout_of(g);
+    const size_t span = FL.span;
+    int rc;
+    if (!recording_matches(rec, kind, g, c, nt)) {
+        // no usable recording: rerun the forward from the initial state u[0]
+        // on workspace copies (both with the level-0 shell)
+        void* p = nullptr;
+        rc = ws_alloc(ctx, FL.bytes(2), &p);
+        if (rc) return rc;
+        float* w0 = FL.at(p, 0);
+        float* w1 = FL.at(p, 1);
+        e = hipMemcpyAsync(w0, g->u[0], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(w1, g->u[0], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(st);
+            ws_free(ctx, p);
+            return dev_fail(e, "adjoint forward copy");
+        }
+        stencil_grid wg = *g;
+        wg.u[0] = w0;
+        wg.u[1] = w1;
+        const int k = ctx->tuning.ckpt_every > 0 ? ctx->tuning.ckpt_every : default_ckpt(nt);
+        rc = run_recorded(ctx, kind, &wg, c, nt, k, &rec);
+        e = hipStreamSynchronize(st);
+        ws_free(ctx, p);
+        if (rc) return rc;
+        if (e != hipSuccess) return dev_fail(e, "adjoint forward");
+    }
+    const int k = rec.every;
+    // workspace: k - 1 state slots (u_{a+1} .. u_{a+k-1}; u_a is the
+    // checkpoint itself), k + 1 lambda fields, and for kind 2 the seven
+    // transposed coefficient arrays
+    const size_t nslot = (size_t)(k - 1), nlam = (size_t)(k + 1);
+    void* p = nullptr;
+    rc = ws_alloc(ctx, FL.bytes(nslot + nlam), &p);
+    if (rc) return rc;
+    void* pc = nullptr;
+    const size_t csize = bf16 ? sizeof(uint16_t) : sizeof(float);
+    if (kind == 2) {
+        rc = ws_alloc(ctx, (FL.lead + 7 * FL.stride) * csize + 256, &pc);
+        if (rc) {
+            ws_free(ctx, p);
+            return rc;
+        }
+    }
+    auto done = [&](hipError_t err, const char* what) {
+        const hipError_t es = hipStreamSynchronize(st);
+        ws_free(ctx, p);
+        if (pc) ws_free(ctx, pc);
+        if (err == hipSuccess) err = es;
+        return err == hipSuccess ? STENCIL_OK : dev_fail(err, what);
+    };
+    void* coefT = pc ? static_cast<char*>(pc) + FL.lead * csize : nullptr;
+    std::vector<float*> lam(nlam);
+    for (size_t i = 0; i < nlam; ++i) lam[i] = FL.at(p, nslot + i);
+    // state slots carry the level-0 shell; lambda fields a zero shell
+    for (size_t i = 0; i < nslot && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(FL.at(p, i), g->u[0], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+    for (size_t i = 0; i < nlam && e == hipSuccess; ++i) e = stn::launch_zero_span(lam[i], span, st);
+    size_t ci = 0;  // lam[ci] holds lambda at the top of the next segment
+    if (e == hipSuccess) e = stn::launch_scale_copy(lam[ci], seed, 1.0f, d, st);
+    if (e == hipSuccess && kind == 2)
+        e = stn::launch_transpose7(coefT, (int64_t)FL.stride, c->arrays, c->sk, bf16, d, st);
+    if (e != hipSuccess) return done(e, "adjoint setup");
+    const stn::host_weights wt = to_weights(c);
+    const int gmax = stn::grad_group_max(kind);
+    std::vector<const float*> L(k + 1), U(k);
+    for (int q = rec.n - 1; q >= 0 && e == hipSuccess; --q) {
+        const int64_t a = (int64_t)q * k;
+        const int m = (int)(std::min<int64_t>(a + k, nt) - a);
+        // U[i] = u_{a+i}, L[j] = lambda_{a+j}
+        U[0] = rec.field((size_t)q);
+        for (int i = 1; i < m; ++i) U[i] = FL.at(p, (size_t)(i - 1));
+        for (int j = 0; j <= m; ++j) L[j] = lam[(ci + (size_t)(m - j)) % nlam];
+        for (int i = 1; i < m && e == hipSuccess; ++i)
+            e = stn::launch_naive_step(kind, bf16, U[i - 1], nullptr, const_cast<float*>(U[i]),
+                                       c->arrays, c->sk, d, wt, 0, st);
+        for (int j = m - 1; j >= 0 && e == hipSuccess; --j) {
+            float* out = const_cast<float*>(L[j]);
+            e = kind == 2 ? stn::launch_naive_step(2, bf16, L[j + 1], nullptr, out, coefT,
+                                                   (int64_t)FL.stride, d, wt, 0, st)
+                          : stn::launch_adj25_step(bf16, L[j + 1], out, c->arrays, c->sk, d, 0, st);
+        }
+        // gradient terms of steps a .. b-1: lambda_{s+1} with u_s, in groups
+        const int ng = (m + gmax - 1) / gmax;
+        for (int gi = 0, s0 = 0; gi < ng && e == hipSuccess; ++gi) {
+            const int cnt = m / ng + (gi < m % ng ? 1 : 0);
+            e = stn::launch_jacobi_grad(kind, cnt, &U[s0], &L[s0 + 1], g_c, c->sk, d, 0, st);
+            s0 += cnt;
+        }
+        ci = (ci + (size_t)m) % nlam;
+    }
+    if (e == hipSuccess) e = stn::launch_scale_copy(g_u0, lam[ci], 1.0f, d, st);
+    return done(e, "adjoint");
+}
+
 }  // namespace
 
 extern "C" {
@@ -602,8 +730,9 @@ int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
         ctx->tuning.dw % (2 * kind_radius(k)) != 0)
         return fail(STENCIL_ERR_INVALID, "dw=%d is not a multiple of 2R=%d", ctx->tuning.dw,
                     2 * kind_radius(k));
-    if (ctx->tuning.ckpt_every > 0 && k != 5)
-        return fail(STENCIL_ERR_UNSUPPORTED, "checkpoint recording is provided for kind 5 only");
+    if (ctx->tuning.ckpt_every > 0 && k != 2 && k != 3 && k != 5)
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "checkpoint recording is provided for kinds 2, 3 and 5 (those with an adjoint)");
     const int slot = kind_leapfrog(k) ? (int)((nt + 1) % 2) : (int)(nt % 2);
     if (nt == 0 || empty(grid)) {
         if (result_slot) *result_slot = slot;
@@ -631,23 +760,29 @@ int stencil_adjoint(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* gri
                     const stencil_coeffs* coeffs, int64_t nt, const float* seed, float* grad_u0,
                     float* grad_um1, double* grad_c) {
     if (!ctx) return fail(STENCIL_ERR_INVALID, "ctx is NULL");
-    if ((int)kind != 5)
-        return fail(STENCIL_ERR_UNSUPPORTED, "the adjoint is provided for kind 5 (25PT_WAVE_VARC)");
-    int rc = validate_grid(5, grid);
+    const int k = (int)kind;
+    if (k != 2 && k != 3 && k != 5)
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "the adjoint is provided for kinds 2, 3 (Jacobi, variable coefficients) and 5");
+    int rc = validate_grid(k, grid);
     if (rc) return rc;
-    rc = validate_coeffs(5, grid, coeffs);
+    rc = validate_coeffs(k, grid, coeffs);
     if (rc) return rc;
     if (nt < 0) return fail(STENCIL_ERR_INVALID, "nt=%lld is negative", (long long)nt);
-    if (!seed || !grad_u0 || !grad_um1 || !grad_c)
+    if (!seed || !grad_u0 || !grad_c)
         return fail(STENCIL_ERR_INVALID, "adjoint field pointer is NULL");
+    if (k == 5 && !grad_um1) return fail(STENCIL_ERR_INVALID, "grad_um1 is NULL");
+    if (k != 5 && grad_um1)
+        return fail(STENCIL_ERR_INVALID, "grad_um1 must be NULL for the Jacobi kinds (one initial level)");
     if (empty(grid)) return STENCIL_OK;
     if (ctx->scheme == STENCIL_BLOCKED) {
         // a missing recording is rebuilt with the context's (blocked) forward
-        rc = check_blocked(ctx, 5, grid);
+        rc = check_blocked(ctx, k, grid);
         if (rc) return rc;
     }
     rc = set_device(ctx);
     if (rc) return rc;
+    if (k != 5) return run_adjoint_jacobi(ctx, k, grid, coeffs, nt, seed, grad_u0, grad_c);
     return run_adjoint(ctx, grid, coeffs, nt, seed, grad_u0, grad_um1, grad_c);
 }
 

@@ -166,10 +166,27 @@ def test_adjoint_argument_errors():
     g = grid(halo=4)
     c = coeffs(5, g)
     f = ctypes.c_void_p(FAKE)
-    assert lib.stencil_adjoint(h, 3, ctypes.byref(g), ctypes.byref(c), 5, f, f, f, f) == 2
+    # kinds without an adjoint
+    for kind in (1, 4):
+        ck = coeffs(kind, g)
+        assert lib.stencil_adjoint(h, kind, ctypes.byref(g), ctypes.byref(ck), 5, f, f, None,
+                                   f) == 2
     assert lib.stencil_adjoint(h, 5, ctypes.byref(g), ctypes.byref(c), -1, f, f, f, f) == 1
     assert lib.stencil_adjoint(h, 5, ctypes.byref(g), ctypes.byref(c), 5, None, f, f, f) == 1
+    assert lib.stencil_adjoint(h, 5, ctypes.byref(g), ctypes.byref(c), 5, f, f, None, f) == 1
     assert lib.stencil_adjoint(None, 5, ctypes.byref(g), ctypes.byref(c), 5, f, f, f, f) == 1
+    # Jacobi kinds: one initial level, so no grad_um1; K FP64 gradient arrays
+    for kind in (2, 3):
+        gk = grid(halo=st.RADIUS[kind])
+        ck = coeffs(kind, gk)
+        assert lib.stencil_adjoint(h, kind, ctypes.byref(gk), ctypes.byref(ck), 5, f, f, f,
+                                   f) == 1 and "grad_um1" in msg()
+        assert lib.stencil_adjoint(h, kind, ctypes.byref(gk), ctypes.byref(ck), 5, f, f, None,
+                                   None) == 1
+        # an empty grid returns before any device call
+        ge = grid(halo=st.RADIUS[kind], nx=0)
+        assert lib.stencil_adjoint(h, kind, ctypes.byref(ge), ctypes.byref(ck), 5, f, f, None,
+                                   f) == 0
     lib.stencil_destroy(h)
 
 
