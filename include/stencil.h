@@ -8,8 +8,9 @@
  *   - a one-sweep-per-step scheme ("naive", Sect. 4.1),
  *   - a temporally blocked scheme: diamond tiles along y with a wavefront
  *     along z (Sect. 4.2-4.3 and 5.1),
- *   - the adjoint (reverse time stepping) of the leapfrog with c(x), which
- *     the paper does not treat: it is the transpose of the Fig. 1e recurrence.
+ *   - the adjoints (reverse time stepping) of the variable-coefficient
+ *     Jacobi stencils of Fig. 1c and 1d and of the leapfrog with c(x), which
+ *     the paper does not treat: the transposes of those recurrences.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -114,8 +115,9 @@ typedef struct {
     int32_t xtile;       /* reserved, 0 */
     int32_t zchunk;      /* planes per z-chunk of one workgroup (parallelism along z);
                             0 = the library's choice */
-    int32_t ckpt_every;  /* checkpoint interval recorded by stencil_run() for kind 5;
-                            0 = no recording */
+    int32_t ckpt_every;  /* checkpoint interval k recorded by stencil_run() for the kinds
+                            with an adjoint (2, 3, 5); 0 = no recording; 1 = every
+                            level (no recomputation in the adjoint, nt + 1 fields) */
     int64_t workspace_limit; /* bytes the context may allocate; 0 = no limit */
 } stencil_tuning;
 
@@ -131,14 +133,33 @@ int stencil_create(stencil_ctx** out, stencil_scheme scheme, const stencil_tunin
 /* Advance `nt` >= 0 time steps in place (Fig. 1b-1e, two-buffer storage as
    above).  On return *result_slot (if not NULL) is the index of u[] that holds
    level nt: nt % 2 for kinds 1-3, (nt + 1) % 2 for kinds 4-5 (the other slot
-   then holds u_{nt-1}).  nt = 0 is a no-op.  For kind 5 with ckpt_every > 0
-   the context records (u_{n-1}, u_n) for n = 0, k, 2k, ... < nt (k =
-   ckpt_every) for a later stencil_adjoint(); the recording is replaced by the
-   next recording run. */
+   then holds u_{nt-1}).  nt = 0 is a no-op.  For kinds 2, 3 and 5 with
+   ckpt_every = k > 0 the context records the state at n = 0, k, 2k, ... < nt
+   (u_n; for kind 5 the pair (u_{n-1}, u_n)) for a later stencil_adjoint();
+   the recording is replaced by the next recording run.  With k = 1 every
+   level is recorded and the sweeps write straight into the recording (the
+   naive sweep is used whatever the scheme); the buffers then also receive
+   the level-0 shell, as with STENCIL_BLOCKED, and for kinds 2-3 the buffer
+   that does not hold level nt is left unspecified. */
 int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
                 const stencil_coeffs* coeffs, int64_t nt, int* result_slot);
 
-/* Reverse time stepping for kind 5 (STENCIL_25PT_WAVE_VARC).  With
+/* Reverse time stepping (adjoint) for kinds 2, 3 and 5.
+
+   Kinds 2 and 3 (Fig. 1c, 1d).  With A = A(W) the sweep operator on the
+   interior (fixed shell), u_{t+1} = A u_t; for a loss with seed
+   lambda_nt = dJ/du_nt the adjoint recurrence is lambda_t = A^T lambda_{t+1}
+   and the outputs are
+       grad_u0     = dJ/du_0 = lambda_0                                (FP32),
+       grad_c + k*sk = dJ/dW_k = sum_{t=0}^{nt-1} lambda_{t+1} * tap_k(u_t)  (FP64),
+   tap_k the value W_k multiplies in the update of Fig. 1c / 1d (u at the
+   neighbour for kind 2, u(p) for W_0 and the pair sum at radius r for
+   W_{3(r-1)+1+a} of kind 3), boundary shell values included.  grad_c holds
+   K FP64 arrays at the coefficients' element stride sk; grad_um1 must be
+   NULL.  BF16 coefficients are differentiated at their FP32 expansion.
+   Without a matching recording grid->u[0] must hold u_0.
+
+   Kind 5 (STENCIL_25PT_WAVE_VARC).  With
    M = 2I + diag(c) L8 the forward map is u_{n+1} = M u_n - u_{n-1}; for a
    loss with seed lambda_nt = dJ/du_nt the adjoint recurrence is
        lambda_n = 2 lambda_{n+1} - lambda_{n+2} + L8(c * lambda_{n+1}),
@@ -146,14 +167,18 @@ int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
        grad_u0  = dJ/du_0    = lambda_0,
        grad_um1 = dJ/du_{-1} = -lambda_1,
        grad_c   = dJ/dc      = sum_{n=0}^{nt-1} lambda_{n+1} * L8(u_n)   (FP64).
-   Forward states are rebuilt from the context's recording when it matches
-   (same sizes, strides, coefficient pointer and nt; made by stencil_run with
-   ckpt_every > 0); otherwise grid->u[0], grid->u[1] must hold the INITIAL
-   (u_{-1}, u_0) and the forward pass is recomputed with checkpoints first.
+
+   All kinds.  Forward states are rebuilt from the context's recording when
+   it matches (same kind, sizes, strides, coefficient pointer and stride, and
+   nt; made by stencil_run with ckpt_every > 0); otherwise grid->u[] must hold
+   the INITIAL state (kind 5: u[0] = u_{-1}, u[1] = u_0) and the forward pass
+   is recomputed with checkpoints first (ckpt_every, or about sqrt(nt) if 0).
    seed, grad_u0, grad_um1 are FP32 and grad_c FP64 padded fields with the
-   grid's strides; only their interiors are read or written.  grad_c is
-   overwritten (not accumulated).  The context allocates ~ (ckpt_every + 4)
-   fields of workspace plus one FP64 field. */
+   grid's strides; only their interiors are read or written.  The gradients
+   are overwritten (not accumulated).  Every level reads the boundary shell of
+   the level-0 buffer.  The context allocates ~ (ckpt_every + 4) fields of
+   workspace (kinds 2-3: ~ 2 ckpt_every + 9, plus 7 coefficient arrays for
+   kind 2). */
 int stencil_adjoint(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
                     const stencil_coeffs* coeffs, int64_t nt, const float* seed,
                     float* grad_u0, float* grad_um1, double* grad_c);

@@ -365,7 +365,9 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
 // Jacobi kinds.  A segment runs on a grid whose u[0], u[1] are the buffers
 // holding (u_{t-1}, u_t) (leapfrog) or (u_t, the other buffer) (Jacobi), so
 // the two-buffer convention is the same as in one long run.  Jacobi
-// checkpoints get the boundary shell of u[0], the level-0 buffer.
+// checkpoints get the boundary shell of u[0], the level-0 buffer.  With k = 1
+// (every level recorded) a Jacobi forward writes each level straight into
+// its checkpoint, so recording costs no extra pass over the lattice.
 int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
                  int64_t nt, int k, stencil_ctx::recording* rec) {
     const field_layout FL = layout_of(g);
@@ -373,7 +375,9 @@ int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stenci
     const bool lf = kind_leapfrog(kind);
     const size_t nf = lf ? 2 : 1;
     const int n = (int)((nt + k - 1) / k);
-    const size_t need = FL.bytes(nf * (size_t)n);
+    // leapfrog with k = 1: one field per level u_{-1} .. u_{nt-1}
+    const bool lf_all = lf && k == 1;
+    const size_t need = FL.bytes(lf_all ? (size_t)nt + 1 : nf * (size_t)n);
     if (!rec->buf || rec->bytes < need) {
         if (rec->buf) ws_free(ctx, rec->buf);
         rec->buf = nullptr;
@@ -389,25 +393,76 @@ int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stenci
     rec->lead = FL.lead;
     rec->stride = FL.stride;
     rec->n = n;
-    for (int q = 0; q < n; ++q) {
-        const int64_t t = (int64_t)q * k;
-        const int64_t steps = std::min<int64_t>(k, nt - t);
-        stencil_grid sub = *g;
-        sub.u[0] = g->u[t % 2];        // leapfrog: u_{t-1}; Jacobi: u_t
-        sub.u[1] = g->u[(t + 1) % 2];  // leapfrog: u_t
-        hipError_t e = hipMemcpyAsync(FL.at(rec->buf, nf * (size_t)q), sub.u[0],
-                                      span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
-        if (e == hipSuccess && lf)
-            e = hipMemcpyAsync(FL.at(rec->buf, 2 * (size_t)q + 1), sub.u[1],
-                               span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
-        if (e == hipSuccess && !lf && t % 2 == 1)
-            e = stn::launch_copy_shell(FL.at(rec->buf, (size_t)q),
-                                       static_cast<const float*>(g->u[0]), to_dims(g),
-                                       kind_radius(kind), ctx->stream);
-        if (e != hipSuccess) return dev_fail(e, "checkpoint copy");
-        const int rc = ctx->scheme == STENCIL_NAIVE ? run_naive(ctx, kind, &sub, c, steps)
-                                                    : run_blocked(ctx, kind, &sub, c, steps);
-        if (rc) return rc;
+    if (!lf && k == 1) {
+        // every level is a checkpoint: the sweeps write straight into the
+        // recording (level-0 shell on every field), the last into the buffer
+        // that holds level nt
+        const stn::dims d = to_dims(g);
+        const stn::host_weights wt = to_weights(c);
+        const bool bf16 = c->dtype == STENCIL_BF16;
+        const float* u0 = static_cast<const float*>(g->u[0]);
+        hipError_t e = hipMemcpyAsync(FL.at(rec->buf, 0), u0, span * sizeof(float),
+                                      hipMemcpyDeviceToDevice, ctx->stream);
+        for (int i = 1; i < n && e == hipSuccess; ++i)
+            e = stn::launch_copy_shell(FL.at(rec->buf, (size_t)i), u0, d, kind_radius(kind),
+                                       ctx->stream);
+        for (int64_t t = 0; t < nt && e == hipSuccess; ++t) {
+            float* out = t + 1 < nt ? FL.at(rec->buf, (size_t)(t + 1))
+                                    : static_cast<float*>(g->u[nt % 2]);
+            e = stn::launch_naive_step(kind, bf16, FL.at(rec->buf, (size_t)t), nullptr, out,
+                                       c->arrays, c->sk, d, wt, ctx->tuning.zchunk, ctx->stream);
+        }
+        if (e != hipSuccess) return dev_fail(e, "recorded forward");
+    } else if (lf_all) {
+        // every level recorded, field i = u_{i-1}: the sweeps write each level
+        // into its own field (level-0 shell on every field), the last into
+        // the caller's buffer for level nt, and u_{nt-1} is copied into the
+        // other buffer, as the two-buffer convention asks
+        const stn::dims d = to_dims(g);
+        const stn::host_weights wt = to_weights(c);
+        const bool bf16 = c->dtype == STENCIL_BF16;
+        const float* u0 = static_cast<const float*>(g->u[1]);
+        hipError_t e = hipMemcpyAsync(FL.at(rec->buf, 0), g->u[0], span * sizeof(float),
+                                      hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(FL.at(rec->buf, 1), u0, span * sizeof(float),
+                               hipMemcpyDeviceToDevice, ctx->stream);
+        for (int64_t i = 2; i <= nt && e == hipSuccess; ++i)
+            e = stn::launch_copy_shell(FL.at(rec->buf, (size_t)i), u0, d, kind_radius(kind),
+                                       ctx->stream);
+        for (int64_t t = 0; t < nt && e == hipSuccess; ++t) {
+            float* out = t + 1 < nt ? FL.at(rec->buf, (size_t)(t + 2))
+                                    : static_cast<float*>(g->u[(nt + 1) % 2]);
+            e = stn::launch_naive_step(kind, bf16, FL.at(rec->buf, (size_t)(t + 1)),
+                                       FL.at(rec->buf, (size_t)t), out, c->arrays, c->sk, d, wt,
+                                       ctx->tuning.zchunk, ctx->stream);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->u[nt % 2], FL.at(rec->buf, (size_t)nt), span * sizeof(float),
+                               hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) return dev_fail(e, "recorded forward");
+    } else {
+        for (int q = 0; q < n; ++q) {
+            const int64_t t = (int64_t)q * k;
+            const int64_t steps = std::min<int64_t>(k, nt - t);
+            stencil_grid sub = *g;
+            sub.u[0] = g->u[t % 2];        // leapfrog: u_{t-1}; Jacobi: u_t
+            sub.u[1] = g->u[(t + 1) % 2];  // leapfrog: u_t
+            hipError_t e = hipMemcpyAsync(FL.at(rec->buf, nf * (size_t)q), sub.u[0],
+                                          span * sizeof(float), hipMemcpyDeviceToDevice,
+                                          ctx->stream);
+            if (e == hipSuccess && lf)
+                e = hipMemcpyAsync(FL.at(rec->buf, 2 * (size_t)q + 1), sub.u[1],
+                                   span * sizeof(float), hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess && !lf && t % 2 == 1)
+                e = stn::launch_copy_shell(FL.at(rec->buf, (size_t)q),
+                                           static_cast<const float*>(g->u[0]), to_dims(g),
+                                           kind_radius(kind), ctx->stream);
+            if (e != hipSuccess) return dev_fail(e, "checkpoint copy");
+            const int rc = ctx->scheme == STENCIL_NAIVE ? run_naive(ctx, kind, &sub, c, steps)
+                                                        : run_blocked(ctx, kind, &sub, c, steps);
+            if (rc) return rc;
+        }
     }
     rec->valid = true;
     rec->kind = kind;
@@ -421,8 +476,8 @@ int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stenci
 
 bool recording_matches(const stencil_ctx::recording& r, int kind, const stencil_grid* g,
                        const stencil_coeffs* c, int64_t nt) {
-    return r.valid && r.kind == kind && r.sk == c->sk && r.nx == g->nx && r.ny == g->ny && r.nz == g->nz && r.halo == g->halo &&
-           r.sy == g->sy && r.sz == g->sz && r.nt == nt && r.coef == c->arrays &&
+    return r.valid && r.kind == kind && r.sk == c->sk && r.nx == g->nx && r.ny == g->ny &&
+           r.nz == g->nz && r.halo == g->halo && r.sy == g->sy && r.sz == g->sz && r.nt == nt && r.coef == c->arrays &&
            r.dtype == (int)c->dtype;
 }
 
@@ -531,19 +586,26 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
         std::swap(cur, nxt);
         return r;
     };
-    for (int q = rec.n - 1; q >= 0 && e == hipSuccess; --q) {
-        const int64_t a = (int64_t)q * k;
-        const int64_t b = std::min<int64_t>(a + k, nt);
-        seg0 = rec.field(2 * (size_t)q);
-        seg1 = rec.field(2 * (size_t)q + 1);
+    // k = 1: every level is recorded (field i = u_{i-1}), so the whole run is
+    // one segment and nothing is recomputed
+    const bool all = k == 1;
+    for (int q = all ? 0 : rec.n - 1; q >= 0 && e == hipSuccess; --q) {
+        const int64_t a = all ? 0 : (int64_t)q * k;
+        const int64_t b = all ? nt : std::min<int64_t>(a + k, nt);
+        if (!all) {
+            seg0 = rec.field(2 * (size_t)q);
+            seg1 = rec.field(2 * (size_t)q + 1);
+        }
         // slot i holds u_{a-1+i}
-        for (int64_t i = 1; i + a < b && e == hipSuccess; ++i)
+        for (int64_t i = 1; !all && i + a < b && e == hipSuccess; ++i)
             e = stn::launch_naive_step(5, bf16, slot((int)i), slot((int)i - 1), slot((int)i + 1),
                                        c->arrays, c->sk, d, wt, 0, st);
         // reverse steps b-1 .. a in groups of three: the middle step of a
         // group also adds the gradient terms of its two neighbours, so the
         // FP64 gradient is read and written once per group
-        auto U = [&](int64_t n) -> const float* { return slot((int)(n - a + 1)); };
+        auto U = [&](int64_t n) -> const float* {
+            return all ? rec.field((size_t)(n + 1)) : slot((int)(n - a + 1));
+        };
         for (int64_t s = b - 1; s >= a && e == hipSuccess;) {
             const int64_t left = s - a + 1;
             if (left >= 3) {
@@ -621,10 +683,12 @@ int run_adjoint_jacobi(stencil_ctx* ctx, int kind, const stencil_grid* g,
         if (e != hipSuccess) return dev_fail(e, "adjoint forward");
     }
     const int k = rec.every;
+    const int gmax = stn::grad_group_max(kind);
     // workspace: k - 1 state slots (u_{a+1} .. u_{a+k-1}; u_a is the
-    // checkpoint itself), k + 1 lambda fields, and for kind 2 the seven
+    // checkpoint itself), a ring of lambda fields (the one being computed and
+    // those the pending gradient group still reads), and for kind 2 the seven
     // transposed coefficient arrays
-    const size_t nslot = (size_t)(k - 1), nlam = (size_t)(k + 1);
+    const size_t nslot = (size_t)(k - 1), nlam = (size_t)std::max(k, gmax) + 1;
     void* p = nullptr;
     rc = ws_alloc(ctx, FL.bytes(nslot + nlam), &p);
     if (rc) return rc;
@@ -651,40 +715,48 @@ int run_adjoint_jacobi(stencil_ctx* ctx, int kind, const stencil_grid* g,
     for (size_t i = 0; i < nslot && e == hipSuccess; ++i)
         e = hipMemcpyAsync(FL.at(p, i), g->u[0], span * sizeof(float), hipMemcpyDeviceToDevice, st);
     for (size_t i = 0; i < nlam && e == hipSuccess; ++i) e = stn::launch_zero_span(lam[i], span, st);
-    size_t ci = 0;  // lam[ci] holds lambda at the top of the next segment
-    if (e == hipSuccess) e = stn::launch_scale_copy(lam[ci], seed, 1.0f, d, st);
+    // lambda_s lives in lam[(nt - s) % nlam]
+    auto lam_at = [&](int64_t s) { return lam[(size_t)((nt - s) % (int64_t)nlam)]; };
+    if (e == hipSuccess) e = stn::launch_scale_copy(lam_at(nt), seed, 1.0f, d, st);
     if (e == hipSuccess && kind == 2)
         e = stn::launch_transpose7(coefT, (int64_t)FL.stride, c->arrays, c->sk, bf16, d, st);
     if (e != hipSuccess) return done(e, "adjoint setup");
     const stn::host_weights wt = to_weights(c);
-    const int gmax = stn::grad_group_max(kind);
-    std::vector<const float*> L(k + 1), U(k);
+    // pending gradient group: (u_s, lambda_{s+1}) for the most recent steps;
+    // it is flushed when full and, when the states are segment slots that the
+    // next segment overwrites (k > 1), at the end of every segment
+    std::vector<const float*> PU, PL, U(k);
+    auto flush = [&]() {
+        hipError_t r = hipSuccess;
+        if (!PU.empty())
+            r = stn::launch_jacobi_grad(kind, (int)PU.size(), PU.data(), PL.data(), g_c, c->sk, d,
+                                        0, st);
+        PU.clear();
+        PL.clear();
+        return r;
+    };
     for (int q = rec.n - 1; q >= 0 && e == hipSuccess; --q) {
         const int64_t a = (int64_t)q * k;
         const int m = (int)(std::min<int64_t>(a + k, nt) - a);
-        // U[i] = u_{a+i}, L[j] = lambda_{a+j}
+        // U[i] = u_{a+i}: the checkpoint, then the recomputed slots
         U[0] = rec.field((size_t)q);
         for (int i = 1; i < m; ++i) U[i] = FL.at(p, (size_t)(i - 1));
-        for (int j = 0; j <= m; ++j) L[j] = lam[(ci + (size_t)(m - j)) % nlam];
         for (int i = 1; i < m && e == hipSuccess; ++i)
             e = stn::launch_naive_step(kind, bf16, U[i - 1], nullptr, const_cast<float*>(U[i]),
                                        c->arrays, c->sk, d, wt, 0, st);
-        for (int j = m - 1; j >= 0 && e == hipSuccess; --j) {
-            float* out = const_cast<float*>(L[j]);
-            e = kind == 2 ? stn::launch_naive_step(2, bf16, L[j + 1], nullptr, out, coefT,
-                                                   (int64_t)FL.stride, d, wt, 0, st)
-                          : stn::launch_adj25_step(bf16, L[j + 1], out, c->arrays, c->sk, d, 0, st);
+        for (int64_t s = a + m - 1; s >= a && e == hipSuccess; --s) {
+            e = kind == 2 ? stn::launch_naive_step(2, bf16, lam_at(s + 1), nullptr, lam_at(s),
+                                                   coefT, (int64_t)FL.stride, d, wt, 0, st)
+                          : stn::launch_adj25_step(bf16, lam_at(s + 1), lam_at(s), c->arrays,
+                                                   c->sk, d, 0, st);
+            PU.push_back(U[s - a]);
+            PL.push_back(lam_at(s + 1));
+            if (e == hipSuccess && (int)PU.size() == gmax) e = flush();
         }
-        // gradient terms of steps a .. b-1: lambda_{s+1} with u_s, in groups
-        const int ng = (m + gmax - 1) / gmax;
-        for (int gi = 0, s0 = 0; gi < ng && e == hipSuccess; ++gi) {
-            const int cnt = m / ng + (gi < m % ng ? 1 : 0);
-            e = stn::launch_jacobi_grad(kind, cnt, &U[s0], &L[s0 + 1], g_c, c->sk, d, 0, st);
-            s0 += cnt;
-        }
-        ci = (ci + (size_t)m) % nlam;
+        if (e == hipSuccess && k > 1) e = flush();
     }
-    if (e == hipSuccess) e = stn::launch_scale_copy(g_u0, lam[ci], 1.0f, d, st);
+    if (e == hipSuccess) e = flush();
+    if (e == hipSuccess) e = stn::launch_scale_copy(g_u0, lam_at(0), 1.0f, d, st);
     return done(e, "adjoint");
 }
 

@@ -8,6 +8,7 @@
 // of width R is staged in LDS (double buffered, one barrier per plane) for the
 // in-plane neighbours.  x is the lane index, so every global access of a wave
 // is one contiguous 256-byte row.  Coefficients are read once per point.
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -204,30 +205,54 @@ hipError_t launch_kind(const float* cur, const float* prev, float* out, const vo
     return hipGetLastError();
 }
 
-// One workgroup per padded (y, z) row: rows in the shell are copied whole,
-// interior rows only at their 2r boundary columns.
-__global__ void copy_shell_kernel(float* dst, const float* src, int nx, int ny, int nz, int r,
-                                  int64_t sy, int64_t sz, int64_t org) {
+// Boundary shell copy in two launches.  Rows that lie in the shell (y or z
+// outside the interior) are copied whole, one workgroup per row; interior rows
+// contribute their 2r boundary points, one thread per point.
+__global__ void copy_shell_rows_kernel(float* dst, const float* src, int nx, int ny, int nz,
+                                       int r, int64_t sy, int64_t sz, int64_t org) {
     const int rows_y = ny + 2 * r;
-    const int y = (int)(blockIdx.x % rows_y) - r;
-    const int z = (int)(blockIdx.x / rows_y) - r;
+    int b = (int)blockIdx.x, y, z;
+    if (b < 2 * r * rows_y) {  // the 2r shell planes, every row
+        const int zi = b / rows_y;
+        z = zi < r ? zi - r : nz + zi - r;
+        y = b % rows_y - r;
+    } else {  // interior planes, the 2r shell rows
+        b -= 2 * r * rows_y;
+        z = b / (2 * r);
+        const int yi = b % (2 * r);
+        y = yi < r ? yi - r : ny + yi - r;
+    }
     const int64_t o = org + (int64_t)z * sz + (int64_t)y * sy;
-    if (y < 0 || y >= ny || z < 0 || z >= nz) {
-        for (int x = (int)threadIdx.x - r; x < nx + r; x += blockDim.x) dst[o + x] = src[o + x];
-    } else if ((int)threadIdx.x < 2 * r) {
-        const int x = (int)threadIdx.x < r ? (int)threadIdx.x - r : nx + (int)threadIdx.x - r;
-        dst[o + x] = src[o + x];
+    for (int x = (int)threadIdx.x - r; x < nx + r; x += blockDim.x) dst[o + x] = src[o + x];
+}
+
+__global__ void copy_shell_cols_kernel(float* dst, const float* src, int nx, int ny, int nz,
+                                       int r, int64_t sy, int64_t sz, int64_t org) {
+    const int64_t n = (int64_t)ny * nz * 2 * r;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = i / (2 * r);
+        const int c = (int)(i % (2 * r));
+        const int64_t y = row % ny, z = row / ny;
+        const int x = c < r ? c - r : nx + c - r;
+        const int64_t o = org + z * sz + y * sy + x;
+        dst[o] = src[o];
     }
 }
 
 }  // namespace
 
 hipError_t launch_copy_shell(float* dst, const float* src, const dims& d, int r, hipStream_t s) {
-    const long long rows = (long long)(d.ny + 2 * r) * (d.nz + 2 * r);
-    if (rows <= 0 || d.nx <= 0) return hipSuccess;
-    if (rows > 0x7fffffffLL || r > 32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(copy_shell_kernel, dim3((unsigned)rows), dim3(64), 0, s, dst, src, d.nx,
-                       d.ny, d.nz, r, d.sy, d.sz, d.org());
+    if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return hipSuccess;
+    if (r > 32) return hipErrorInvalidValue;
+    const long long rows = 2LL * r * (d.ny + 2 * r) + 2LL * r * d.nz;
+    if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(copy_shell_rows_kernel, dim3((unsigned)rows), dim3(256), 0, s, dst, src,
+                       d.nx, d.ny, d.nz, r, d.sy, d.sz, d.org());
+    const long long pts = (long long)d.ny * d.nz * 2 * r;
+    const long long blocks = std::min<long long>((pts + 255) / 256, 8192);
+    hipLaunchKernelGGL(copy_shell_cols_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src,
+                       d.nx, d.ny, d.nz, r, d.sy, d.sz, d.org());
     return hipGetLastError();
 }
 

@@ -109,7 +109,7 @@ def test_adjoint_jacobi_schedule_invariance(kind):
     wl = workloads.make(WL[kind], n=(70, 33, 21), nt=nt)
     s = seed_field(wl, 2)
     ref0, refc = grads_gpu(wl, nt, s, k=4)
-    for kw in (dict(k=1), dict(k=6), dict(k=11), dict(k=3, record=False),
+    for kw in (dict(k=1), dict(k=1, record=False), dict(k=6), dict(k=11), dict(k=3, record=False),
                dict(k=5, scheme=st.BLOCKED), dict(k=2, scheme=st.BLOCKED, record=False)):
         g0, gc = grads_gpu(wl, nt, s, **kw)
         assert np.array_equal(g0, ref0), kw
@@ -125,3 +125,23 @@ def test_adjoint_jacobi_nt_zero(kind):
     g0, gc = grads_gpu(wl, 0, s, k=1)
     np.testing.assert_array_equal(oracle.interior(g0, h), oracle.interior(s, h))
     assert not gc.any()
+
+
+@pytest.mark.parametrize("kind,k", [(2, 1), (2, 3), (3, 1), (3, 4)])
+def test_adjoint_jacobi_nonzero_shell(kind, k):
+    """A non-zero boundary shell on u_0 enters the coefficient gradients of
+    the boundary points (their taps read it); the checkpoints and the
+    recomputed levels carry the level-0 shell."""
+    nt = 6
+    wl = workloads.make(WL[kind], n=(66, 35, 19), nt=nt)
+    h = wl.halo
+    rng = np.random.default_rng([1410, 95, kind])
+    shell = rng.uniform(-1, 1, wl.u0.shape).astype(np.float32)
+    inner = (slice(h, -h),) * 3
+    shell[inner] = wl.u0[inner]
+    wl.u0 = shell
+    s = seed_field(wl, 4)
+    g0, gc = grads_gpu(wl, nt, s, k=k)
+    o0, oc = grads_oracle(wl, nt, s)
+    assert rel(g0, o0, h) <= 1e-5
+    assert max(rel(gc[i], oc[i], h) for i in range(gc.shape[0])) <= 1e-5
