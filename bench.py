@@ -10,9 +10,12 @@ inputs resident in HBM.  value = lattice-site updates per second, counting
 only the algorithmic 480^3 * 100 updates (never recomputed halos).
 
 Beside it the other scheme is timed on the same run, both with BF16
-coefficients, and the leapfrog adjoint workload (256^3, 200 steps,
-checkpoints every 14) forward and backward.  The FP64 CPU oracle is timed on
-a bounded sample of the same workload on the host cores.
+coefficients; the 7-point variable-coefficient workload (512^3, 100 steps)
+with both schemes; and the adjoints, forward (recording) and backward: the
+leapfrog with c(x) (256^3, 200 steps; checkpoints every 14 steps and every
+level) and the 7- and 25-point variable-coefficient Jacobi workloads (every
+level recorded).  The FP64 CPU oracle is timed on a bounded sample of the
+same workload on the host cores.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -49,7 +52,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--n", type=int, default=None, help="override the grid size (testing only)")
     ap.add_argument("--adjoint-only", action="store_true",
-                    help="only run the adjoint leg (forward with checkpoints, then the adjoint)")
+                    help="only run the adjoint legs (forward with checkpoints, then the adjoint)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the device-to-device copy probe and print its bandwidth")
     args = ap.parse_args()
@@ -75,7 +78,9 @@ def main():
         print(json.dumps({"copy_probe": probe}), flush=True)
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_leg(st, workloads, torch, np, stream, args)}),
+        print(json.dumps({"adjoint": adjoint_leg(st, workloads, torch, np, stream, args),
+                          "adjoint_jacobi": {workloads.NAMES[i]: jacobi_adjoint_leg(
+                              st, workloads, torch, np, stream, i, args) for i in (3, 4)}}),
               flush=True)
         return
 
@@ -182,8 +187,15 @@ def main():
             extras["7pt_var"] = scheme_leg(st, workloads, model, torch, np, stream, 3)
         try:
             extras["adjoint"] = adjoint_leg(st, workloads, torch, np, stream, args)
-        except Exception as e:  # the adjoint leg reports, it does not sink the line
+        except Exception as e:  # the adjoint legs report, they do not sink the line
             extras["adjoint"] = {"error": str(e)[:200]}
+        for i in (3, 4):
+            try:
+                extras.setdefault("adjoint_jacobi", {})[workloads.NAMES[i]] = \
+                    jacobi_adjoint_leg(st, workloads, torch, np, stream, i, args)
+            except Exception as e:
+                extras.setdefault("adjoint_jacobi", {})[workloads.NAMES[i]] = \
+                    {"error": str(e)[:200]}
     ctx_b.close()
     ctx_n.close()
 
@@ -291,8 +303,24 @@ def scheme_leg(st, workloads, model, torch, np, stream, index, reps=3):
     return out
 
 
+def timed_pair(torch, stream, first, second):
+    """HIP-event seconds of first() and of second(), with a sync in between."""
+    e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+    e0.record(stream)
+    first()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    e2.record(stream)
+    second()
+    e3.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, e2.elapsed_time(e3) / 1e3
+
+
 def adjoint_leg(st, workloads, torch, np, stream, args):
-    """Workload 5: forward (recording checkpoints) and adjoint, GLUP/s each."""
+    """Workload 5: plain forward, then forward (recording) and adjoint with
+    checkpoints every 14 steps (naive and blocked forward) and with every
+    level recorded; GLUP/s each."""
     wl = workloads.make(5)
     h, nt = wl.halo, wl.nt
     lups = wl.lups
@@ -304,40 +332,102 @@ def adjoint_leg(st, workloads, torch, np, stream, args):
     c.copy_(torch.from_numpy(wl.coef))
     d = st.alloc_field(wl.n3, h)
     d.copy_(torch.from_numpy(wl.target))
-    k = workloads.CKPT_EVERY
-    out = {}
-    for scheme, name in ((st.NAIVE, "naive"), (st.BLOCKED, "blocked")):
+    reps = max(1, args.steps // 2)
+    a, b = st.field_like(up, h), st.field_like(u0, h)
+    seed = st.alloc_field(wl.n3, h)
+    g0 = st.alloc_field(wl.n3, h)
+    gm1 = st.alloc_field(wl.n3, h)
+    gc = st.alloc_field(wl.n3, h, dtype=torch.float64)
+    out = {"workload": wl.name}
+    ctx0 = st.Context(st.NAIVE, stream=stream)
+    ts = []
+    for i in range(1 + reps):
+        a.copy_(up)
+        b.copy_(u0)
+        t, _ = timed_pair(torch, stream, lambda: ctx0.run(5, a, b, nt, halo=h, coef=c,
+                                                          w=st.L8_WEIGHTS), lambda: None)
+        ts.append(t)
+    ctx0.close()
+    tp = float(np.median(ts[1:]))
+    out["plain_fwd_glups"] = round(lups / tp / 1e9, 2)
+    for scheme, k, name in ((st.NAIVE, workloads.CKPT_EVERY, "naive_ckpt14"),
+                            (st.BLOCKED, workloads.CKPT_EVERY, "blocked_ckpt14"),
+                            (st.NAIVE, 1, "every_level")):
         ctx = st.Context(scheme, ckpt_every=k, stream=stream)
-        a, b = st.field_like(up, h), st.field_like(u0, h)
         ts_f, ts_a = [], []
-        for i in range(1 + max(1, args.steps // 2)):
+        for i in range(1 + reps):
             a.copy_(up)
             b.copy_(u0)
-            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-            e0.record(stream)
-            slot = ctx.run(5, a, b, nt, halo=h, coef=c, w=st.L8_WEIGHTS)
-            e1.record(stream)
-            uT = (a, b)[slot]
-            seed = st.alloc_field(wl.n3, h)
-            seed.copy_(uT - d)
-            g0 = st.alloc_field(wl.n3, h)
-            gm1 = st.alloc_field(wl.n3, h)
-            gc = st.alloc_field(wl.n3, h, dtype=torch.float64)
-            torch.cuda.synchronize()
-            e1b = torch.cuda.Event(enable_timing=True)
-            e1b.record(stream)
-            ctx.adjoint(up, u0, nt, halo=h, coef=c, w=st.L8_WEIGHTS, seed=seed, grad_u0=g0,
-                        grad_um1=gm1, grad_c=gc)
-            e2.record(stream)
-            torch.cuda.synchronize()
+            slot = [0]
+
+            def fwd():
+                slot[0] = ctx.run(5, a, b, nt, halo=h, coef=c, w=st.L8_WEIGHTS)
+                seed.copy_((a, b)[slot[0]] - d)
+
+            tf, ta = timed_pair(torch, stream, fwd, lambda: ctx.adjoint(
+                up, u0, nt, halo=h, coef=c, w=st.L8_WEIGHTS, seed=seed, grad_u0=g0,
+                grad_um1=gm1, grad_c=gc))
             if i >= 1:
-                ts_f.append(e0.elapsed_time(e1) / 1e3)
-                ts_a.append(e1b.elapsed_time(e2) / 1e3)
-        tf, ta = float(np.median(ts_f)), float(np.median(ts_a))
-        out[name] = {"fwd_glups": round(lups / tf / 1e9, 2), "adj_glups": round(lups / ta / 1e9, 2),
-                     "adj_over_fwd": round(tf / ta, 3)}
+                ts_f.append(tf)
+                ts_a.append(ta)
         ctx.close()
-    out["workload"] = wl.name
+        tf, ta = float(np.median(ts_f)), float(np.median(ts_a))
+        out[name] = {"ckpt_every": k, "fwd_glups": round(lups / tf / 1e9, 2),
+                     "adj_glups": round(lups / ta / 1e9, 2),
+                     "adj_over_plain_fwd": round(tp / ta, 3)}
+    log(f"[bench] leapfrog adjoint: every level {out['every_level']['adj_glups']} GLUP/s "
+        f"({out['every_level']['adj_over_plain_fwd']} of the plain forward)")
+    return out
+
+
+def jacobi_adjoint_leg(st, workloads, torch, np, stream, index, args):
+    """Workload 3 (7-point) or 4 (25-point variable coefficients): plain
+    forward, forward recording every level, and the adjoint with the
+    gradients of all K coefficient arrays; GLUP/s each."""
+    wl = workloads.make(index)
+    h, nt, kind = wl.halo, wl.nt, wl.kind
+    lups = wl.lups
+    K = wl.coef.shape[0]
+    u0 = st.alloc_field(wl.n3, h)
+    u0.copy_(torch.from_numpy(wl.u0))
+    cf = st.alloc_field(wl.n3, h, count=K)
+    cf.copy_(torch.from_numpy(wl.coef))
+    wl.coef = None
+    a, b = st.field_like(u0, h), st.field_like(u0, h)
+    seed = st.alloc_field(wl.n3, h)
+    gen = torch.Generator(device=seed.device)
+    gen.manual_seed(1410 + index)
+    seed[h:-h, h:-h, h:-h].uniform_(-1, 1, generator=gen)
+    g0 = st.alloc_field(wl.n3, h)
+    gc = st.alloc_field(wl.n3, h, count=K, dtype=torch.float64)
+    reps = max(1, args.steps // 2)
+    out = {"workload": wl.name, "ckpt_every": 1}
+    ctx0 = st.Context(st.NAIVE, stream=stream)
+    ctx = st.Context(st.NAIVE, ckpt_every=1, stream=stream)
+    tp, tf, ta = [], [], []
+    for i in range(1 + reps):
+        a.copy_(u0)
+        b.copy_(u0)
+        t, _ = timed_pair(torch, stream, lambda: ctx0.run(kind, a, b, nt, halo=h, coef=cf),
+                          lambda: None)
+        a.copy_(u0)
+        b.copy_(u0)
+        f, g = timed_pair(torch, stream, lambda: ctx.run(kind, a, b, nt, halo=h, coef=cf),
+                          lambda: ctx.adjoint_jacobi(kind, a, b, nt, halo=h, coef=cf, seed=seed,
+                                                     grad_u0=g0, grad_c=gc))
+        if i >= 1:
+            tp.append(t)
+            tf.append(f)
+            ta.append(g)
+    ctx.close()
+    ctx0.close()
+    tp, tf, ta = (float(np.median(x)) for x in (tp, tf, ta))
+    out.update({"plain_fwd_glups": round(lups / tp / 1e9, 2),
+                "rec_fwd_glups": round(lups / tf / 1e9, 2),
+                "adj_glups": round(lups / ta / 1e9, 2),
+                "adj_over_plain_fwd": round(tp / ta, 3)})
+    log(f"[bench] {wl.name} adjoint: {out['adj_glups']} GLUP/s ({out['adj_over_plain_fwd']} of "
+        f"the plain forward)")
     return out
 
 
