@@ -145,3 +145,24 @@ def test_adjoint_jacobi_nonzero_shell(kind, k):
     o0, oc = grads_oracle(wl, nt, s)
     assert rel(g0, o0, h) <= 1e-5
     assert max(rel(gc[i], oc[i], h) for i in range(gc.shape[0])) <= 1e-5
+
+
+@pytest.mark.parametrize("kind,k", [(2, 3), (3, 1)])
+def test_autograd_jacobi_matches_adjoint(kind, k):
+    import torch
+    from paper_1410_3060_amd.autograd import jacobi_var
+    nt = 7
+    wl = workloads.make(WL[kind], n=(48, 33, 21), nt=nt)
+    h = wl.halo
+    u0 = torch.from_numpy(wl.u0).cuda().requires_grad_(True)
+    cf = torch.from_numpy(wl.coef).cuda().requires_grad_(True)
+    s = seed_field(wl, 5)
+    uT = jacobi_var(u0, cf, nt, kind=kind, ckpt_every=k)
+    # loss = <u_T, s>: its gradient with respect to u_T is the seed
+    loss = (uT * torch.from_numpy(s).cuda()).sum()
+    loss.backward()
+    g0, gc = grads_gpu(wl, nt, s, k=k)
+    np.testing.assert_array_equal(oracle.interior(u0.grad.double().cpu().numpy(), h),
+                                  oracle.interior(g0, h))
+    # the library's FP64 gradient rounded once to the coefficients' FP32
+    np.testing.assert_array_equal(cf.grad.cpu().numpy(), gc.astype(np.float32))
