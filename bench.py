@@ -51,6 +51,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--n", type=int, default=None, help="override the grid size (testing only)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line: grid-size sweep (cubes, multiples of 64) of "
+                         "the naive and blocked schemes with every provided diamond width, and the "
+                         "copy bandwidth by working set (one JSON line)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the adjoint legs (forward with checkpoints, then the adjoint)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -76,6 +80,9 @@ def main():
     probe = copy_probe(torch)
     if args.copy_probe:
         print(json.dumps({"copy_probe": probe}), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps(sweep_leg(torch, args)), flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_leg(st, workloads, torch, np, stream, args),
@@ -428,6 +435,37 @@ def jacobi_adjoint_leg(st, workloads, torch, np, stream, index, args):
                 "adj_over_plain_fwd": round(tp / ta, 3)})
     log(f"[bench] {wl.name} adjoint: {out['adj_glups']} GLUP/s ({out['adj_over_plain_fwd']} of "
         f"the plain forward)")
+    return out
+
+
+def sweep_leg(torch, args):
+    """Copy bandwidth by working set (the in-cache and HBM roofs), then for the
+    7-point constant, 7-point and 25-point variable-coefficient stencils at
+    cubes of 64 .. 512 (100 steps) the GLUP/s of the naive sweep and of the
+    blocked scheme at every provided diamond width."""
+    from paper_1410_3060_amd import model, tune
+    out = {"roofs": tune.memory_roofs()}
+    log("[sweep] copy roofs " + ", ".join(f"{r['working_set_MiB']} MiB {r['GBps']:.0f} GB/s"
+                                          for r in out["roofs"]))
+    rows = []
+    nt = 100
+    for kind in (1, 2, 3):
+        for n in range(64, 513, 64):
+            r = tune.autotune(kind, (n, n, n), nt, reps=1)
+            naive = next(x for x in r["results"] if x["scheme"] == "naive")
+            blk = {str(x["dw"]): round(x["glups"], 2) for x in r["results"] if x["scheme"] == "blocked"}
+            bpl = model.naive_code_balance(kind)
+            # bytes the naive sweep touches per step: fields and coefficients
+            ws = (2 + model.NCOEF[kind]) * (n + 2 * model.RADIUS[kind]) ** 3 * 4 / 2 ** 20
+            row = {"kind": kind, "n": n, "nt": nt, "working_set_MiB": round(ws, 1),
+                   "naive_glups": round(naive["glups"], 2),
+                   "naive_alg_GBps": round(naive["glups"] * bpl, 1),
+                   "blocked_glups_by_dw": blk,
+                   "best": {"scheme": r["best"]["scheme"], "dw": r["best"]["dw"],
+                            "glups": round(r["best"]["glups"], 2)}}
+            rows.append(row)
+            log(f"[sweep] kind {kind} {n}^3: naive {row['naive_glups']}, blocked {blk}")
+    out["rows"] = rows
     return out
 
 

@@ -1,0 +1,26 @@
+"""The measured tuner: every candidate runs through the library and the best
+is the fastest measured; the copy-roof probe returns one figure per working
+set."""
+import pytest
+
+import paper_1410_3060_amd as st
+from paper_1410_3060_amd import tune
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("kind,n3", [(2, (70, 40, 30)), (3, (66, 36, 20))])
+def test_autotune_candidates_and_best(kind, n3):
+    r = tune.autotune(kind, n3, 8, reps=1)
+    widths = tune.PROVIDED_DW[st.RADIUS[kind]]
+    assert len(r["results"]) == 1 + len(widths)
+    assert [x["dw"] for x in r["results"][1:]] == list(widths)
+    assert all(x["glups"] > 0 for x in r["results"])
+    assert r["best"]["glups"] == max(x["glups"] for x in r["results"])
+    assert r["library_default_dw"] == st.default_dw(kind)
+
+
+def test_memory_roofs():
+    roofs = tune.memory_roofs((4, 64), reps=3)
+    assert [x["working_set_MiB"] for x in roofs] == [4, 64]
+    assert all(x["GBps"] > 0 for x in roofs)
