@@ -1,12 +1,13 @@
 """Measured choice of the scheme and the diamond width for one problem size.
 
-The paper sizes its diamonds from a cache model (Sect. 5.3) and tunes the
-remaining parameters by measurement (Sect. 5.4).  On MI355X the on-chip block
-is fixed by the compiled kernel configurations, so the choice left to the
-caller is which scheme to run and, for the blocked one, which of the provided
-diamond widths; ``autotune`` times every candidate through the library on
-synthetic inputs of the caller's sizes and returns the fastest.  Only the
-library runs here: nothing in this module computes stencil values.
+The paper auto-tunes the diamond width and the number of wavefront
+frontlines, searching only tiles whose cache block (Sect. 5.3) fits a cache
+size range (Sect. 5.1).  On MI355X the on-chip block of each diamond width is
+fixed by the compiled kernel configurations, so the choice left is which
+scheme to run and, for the blocked one, which of the provided widths;
+``autotune`` times every candidate through the library on synthetic inputs of
+the caller's sizes and returns the fastest.  Only the library runs here:
+nothing in this module computes stencil values.
 
 ``memory_roofs`` measures the attainable bandwidth of a plain device copy as a
 function of its working set: the in-cache roofs (L2, Infinity Cache) and the
