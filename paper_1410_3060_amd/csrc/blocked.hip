@@ -68,13 +68,28 @@ __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
 __device__ __forceinline__ void bstore(rsrc_t r, float v, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
 }
+// Coefficient array k as a buffer.  BF16 arrays are read a 32-bit word at a
+// time (the compiler waits for every 16-bit buffer load at once, which would
+// serialise a level's K loads): the resource starts at the word-aligned
+// address at or below the array and `mis` (0 or 2 bytes) is the array's
+// offset from it.
+struct coef_rsrc {
+    rsrc_t r;
+    uint32_t mis;
+};
 // coefficient loads: FP32, or BF16 expanded exactly to FP32 (as load_coef)
-__device__ __forceinline__ float cload(const float*, rsrc_t r, uint32_t voff, uint32_t soff) {
-    return bload(r, voff, soff);
+__device__ __forceinline__ float cload(const float*, const coef_rsrc& c, uint32_t voff,
+                                       uint32_t soff) {
+    return bload(c.r, voff, soff);
 }
-__device__ __forceinline__ float cload(const uint16_t*, rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0))
-                           << 16);
+__device__ __forceinline__ float cload(const uint16_t*, const coef_rsrc& c, uint32_t voff,
+                                       uint32_t soff) {
+    // the value sits in the high half of the word 2 bytes below it when its
+    // byte offset from the aligned base is 2 mod 4, else in the low half
+    const uint32_t adj = (voff + soff + c.mis) & 2u;
+    const uint32_t vo = voff >= kNone ? voff : voff + c.mis - adj;
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(c.r, vo, soff, 0);
+    return __uint_as_float(adj ? (w & 0xffff0000u) : (w << 16));
 }
 
 template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING, bool G0, int PD>
@@ -122,7 +137,19 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const uint32_t szc = (uint32_t)(sz * CB);
     auto pf = [&](int z) { return (uint32_t)(z + hh) * sz4; };  // field plane bytes
     auto pc_ = [&](int z) { return (uint32_t)(z + hh) * szc; };  // coefficient plane bytes
-    auto crs = [&](int k) { return make_rsrc(coef + (int64_t)k * sk, coef_bytes); };
+    auto crs = [&](int k) -> coef_rsrc {
+        if constexpr (CB == 2) {
+            const uintptr_t a = reinterpret_cast<uintptr_t>(coef + (int64_t)k * sk);
+            const uint32_t mis = (uint32_t)(a & 2u);
+            // every word that holds an element; never beyond 2^31 (kNone stays out)
+            const uint64_t nr = (uint64_t)coef_bytes + mis + 2u;
+            return {make_rsrc(reinterpret_cast<const void*>(a - mis),
+                              (uint32_t)(nr < 0x80000000ull ? nr : 0x80000000ull)),
+                    mis};
+        } else {
+            return {make_rsrc(coef + (int64_t)k * sk, coef_bytes), 0u};
+        }
+    };
     // the tile reaches outside [0, nx) in x: boundary columns hold the shell
     const bool xb = xbase < 0 || xbase + XT > nx;
 
