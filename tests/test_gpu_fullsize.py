@@ -132,3 +132,41 @@ def test_fullsize_adjoint_dot_product():
     print(f"adjoint dot product 256^3 nt=200: <F d, s> = {lhs:.9e}, <d, F^T s> = {rhs:.9e}, "
           f"rel {rel:.2e}")
     assert rel <= 1e-5
+
+
+@pytest.mark.parametrize("index", [3, 4])
+def test_fullsize_jacobi_adjoint_identities(index):
+    """Adjoint of workloads 3 and 4 at full size in the bench's configuration
+    (every level recorded), checked by two identities that hold at any size:
+    the dot product <A^nt d, s> = <d, dJ/du_0> for J = <u_nt, s>, and, since
+    with a zero shell u_nt is homogeneous of degree nt in the coefficients,
+    sum_k <W_k, dJ/dW_k> = nt * J."""
+    import torch
+    wl = workloads.make(index)
+    h, nt, kind = wl.halo, wl.nt, wl.kind
+    K = wl.coef.shape[0]
+    cf = coef_to_dev(wl)
+    wl.coef = None
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1410 + 10 * index)
+    inner = (slice(h, -h),) * 3
+    d = st.alloc_field(wl.n3, h)
+    d[inner].uniform_(-1, 1, generator=gen)
+    s = st.alloc_field(wl.n3, h)
+    s[inner].uniform_(-1, 1, generator=gen)
+    a, b = st.field_like(d, h), st.field_like(d, h)
+    g0 = st.alloc_field(wl.n3, h)
+    gc = st.alloc_field(wl.n3, h, count=K, dtype=torch.float64)
+    with st.Context(st.NAIVE, ckpt_every=1) as ctx:
+        slot = ctx.run(kind, a, b, nt, halo=h, coef=cf)
+        uT = (a, b)[slot]
+        J = float((uT[inner].double() * s[inner].double()).sum())
+        ctx.adjoint_jacobi(kind, a, b, nt, halo=h, coef=cf, seed=s, grad_u0=g0, grad_c=gc)
+        ctx.sync()
+    rhs = float((d[inner].double() * g0[inner].double()).sum())
+    hom = sum(float((gc[k][inner] * cf[k][inner].double()).sum()) for k in range(K))
+    e_dot = abs(J - rhs) / abs(J)
+    e_hom = abs(hom - nt * J) / abs(nt * J)
+    print(f"{wl.name} adjoint: <F d, s> = {J:.9e}, <d, g_u0> = {rhs:.9e} (rel {e_dot:.2e}); "
+          f"sum <W, g_W> / (nt J) - 1 = {e_hom:.2e}")
+    assert e_dot <= 1e-5 and e_hom <= 1e-5
