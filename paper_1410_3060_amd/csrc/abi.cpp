@@ -561,9 +561,11 @@ int run_adjoint(stencil_ctx* ctx, const stencil_grid* g, const stencil_coeffs* c
     if (e != hipSuccess) return done(e, "adjoint coefficient check");
     const bool mu = bad == 0;
     // the boundary shell is taken as time independent: every slot gets the
-    // shell of the buffer holding level 0 (its interior is overwritten)
+    // stencil-deep shell of the buffer holding level 0 (its interior is
+    // written by the recomputation before it is read)
     for (size_t i = 0; i < nslot && e == hipSuccess; ++i)
-        e = hipMemcpyAsync(FL.at(p, i), g->u[1], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+        e = stn::launch_copy_shell(FL.at(p, i), static_cast<const float*>(g->u[1]), d,
+                                   kind_radius(5), st);
     if (e == hipSuccess) e = stn::launch_zero_span(lam_a, span, st);
     if (e == hipSuccess) e = stn::launch_zero_span(lam_b, span, st);
     if (e == hipSuccess)
@@ -711,9 +713,11 @@ int run_adjoint_jacobi(stencil_ctx* ctx, int kind, const stencil_grid* g,
     void* coefT = pc ? static_cast<char*>(pc) + FL.lead * csize : nullptr;
     std::vector<float*> lam(nlam);
     for (size_t i = 0; i < nlam; ++i) lam[i] = FL.at(p, nslot + i);
-    // state slots carry the level-0 shell; lambda fields a zero shell
+    // state slots carry the stencil-deep level-0 shell (their interiors are
+    // recomputed before they are read); lambda fields a zero shell
     for (size_t i = 0; i < nslot && e == hipSuccess; ++i)
-        e = hipMemcpyAsync(FL.at(p, i), g->u[0], span * sizeof(float), hipMemcpyDeviceToDevice, st);
+        e = stn::launch_copy_shell(FL.at(p, i), static_cast<const float*>(g->u[0]), d,
+                                   kind_radius(kind), st);
     for (size_t i = 0; i < nlam && e == hipSuccess; ++i) e = stn::launch_zero_span(lam[i], span, st);
     // lambda_s lives in lam[(nt - s) % nlam]
     auto lam_at = [&](int64_t s) { return lam[(size_t)((nt - s) % (int64_t)nlam)]; };
