@@ -85,9 +85,11 @@ typedef enum {
 
 typedef enum {
     STENCIL_NAIVE = 0,  /* one full sweep per time step (Sect. 4.1) */
-    STENCIL_BLOCKED = 1 /* diamond tiles in y, wavefront in z (Sect. 4.2, 4.3, 5.1); fields
-                           must span less than 2 GiB from their padded origin (the kernel
-                           uses 32-bit byte offsets), else STENCIL_ERR_UNSUPPORTED */
+    STENCIL_BLOCKED = 1 /* diamond tiles in y, wavefront in z (Sect. 4.2, 4.3, 5.1); a
+                           workgroup addresses its z-chunk with 32-bit byte offsets from a
+                           base of its own, so fields of any size work while a window of
+                           2R(L+1) + 2 planes (L = 2 dw / (2R) - 1) stays below 2 GiB, else
+                           STENCIL_ERR_UNSUPPORTED; z-chunks are capped to fit */
 } stencil_scheme;
 
 typedef enum { STENCIL_F32 = 0, STENCIL_BF16 = 1 } stencil_dtype;

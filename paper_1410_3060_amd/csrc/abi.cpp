@@ -252,18 +252,29 @@ int ensure_frontier(stencil_ctx* ctx, size_t bytes) {
     return STENCIL_OK;
 }
 
+// Planes per z-chunk of the blocked kernel whose address window (the chunk
+// plus 2R(L+1) + 1 planes, from a base of the workgroup's own) stays below
+// 2^31 bytes, so that 32-bit offsets reach it; < 1 if none does.
+int64_t blocked_max_zchunk(int kind, int dw, const stencil_grid* g) {
+    const int R = kind_radius(kind);
+    const int L = 2 * (dw / (2 * R)) - 1;
+    const int64_t plane = g->sz * (int64_t)sizeof(float);
+    return (int64_t)0x7fffffff / plane - 2LL * R * (L + 1) - 1;
+}
+
 // Limits of the blocked scheme, checked with the other arguments before any
-// HIP call: a provided diamond width, and 32-bit byte offsets (fields below
-// 2 GiB from their padded origin).
+// HIP call: a provided diamond width, and an address window of one z-chunk
+// plane below 2^31 bytes (planes below about 2^31 / (2R(L+1) + 2) bytes).
 int check_blocked(const stencil_ctx* ctx, int kind, const stencil_grid* g) {
     const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
     if (!stn::blocked_supported(kind, dw))
         return fail(STENCIL_ERR_UNSUPPORTED, "blocked scheme: dw=%d is not provided for kind %d", dw,
                     kind);
-    const size_t fbytes = (size_t)field_span(g) * sizeof(float);
-    if (fbytes >= ((size_t)1 << 31))
+    if (blocked_max_zchunk(kind, dw, g) < 1)
         return fail(STENCIL_ERR_UNSUPPORTED,
-                    "blocked scheme: a field spans %zu bytes, the limit is 2 GiB", fbytes);
+                    "blocked scheme: a plane of %lld bytes is too large for the 2 GiB address "
+                    "window of a z-chunk",
+                    (long long)(g->sz * (int64_t)sizeof(float)));
     return STENCIL_OK;
 }
 
@@ -315,6 +326,7 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         if (e == hipSuccess) e = stn::launch_copy_shell(w1, shell, d, R, ctx->stream);
         if (e != hipSuccess) return dev_fail(e, "shell copy");
     }
+    const int64_t zmax = blocked_max_zchunk(kind, dw, g);
     const int xomax = stn::blocked_max_xo(kind, dw);
     const int gx = (g->nx + xomax - 1) / xomax;
     const int xo = (g->nx + gx - 1) / gx;
@@ -334,8 +346,8 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         a.first_centre = row.first_centre;
         a.n_diamonds = row.n_diamonds;
         a.dw = dw;
-        a.field_bytes = (uint32_t)fbytes;
-        a.coef_bytes = (uint32_t)(FL.span * (bf16 ? 2 : 4));
+        a.field_bytes = fbytes;
+        a.coef_bytes = FL.span * (bf16 ? 2 : 4);
         a.xo = xo;
         a.gx = gx;
         int zc = ctx->tuning.zchunk;
@@ -347,6 +359,7 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
             gz = std::max(1LL, std::min(gz, (long long)g->nz / zmin));
             zc = (int)((g->nz + gz - 1) / gz);
         }
+        zc = (int)std::min<int64_t>(zc, zmax);
         a.zchunk = zc;
         a.gz = (g->nz + zc - 1) / zc;
         if ((long long)a.n_diamonds * a.gx * a.gz > 0x7fffffffLL)

@@ -27,8 +27,10 @@ struct blocked_row_args {
     int gx;       // x tiles
     int zchunk;   // planes per z-chunk
     int gz;       // z-chunks
-    uint32_t field_bytes;  // bytes of one field from its padded origin (< 2^31)
-    uint32_t coef_bytes;   // bytes of one coefficient array from its padded origin
+    uint64_t field_bytes;  // bytes of one field from its padded origin
+    uint64_t coef_bytes;   // bytes of one coefficient array from its padded origin
+    // (a workgroup addresses a window of zchunk + 2R(L+1) + 1 planes from a
+    // base of its own with 32-bit offsets: the window must stay below 2^31 bytes)
 };
 
 bool blocked_supported(int kind, int dw);

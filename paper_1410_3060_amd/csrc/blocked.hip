@@ -92,11 +92,12 @@ __device__ __forceinline__ float cload(const uint16_t*, const coef_rsrc& c, uint
     return __uint_as_float(adj ? (w & 0xffff0000u) : (w << 16));
 }
 
-template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING, bool G0, int PD>
+template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING, bool G0, int PD, bool WIN>
 __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const float* ftop_o, const float* fsub_o, float* ftop_n, float* fsub_n,
     const CT* __restrict__ coef, int64_t sk, int nx, int ny, int nz, int hh, int64_t sy,
-    int64_t sz, uint32_t field_bytes, uint32_t coef_bytes, weights wt, int t0, int nt,
+    int64_t sz, std::conditional_t<WIN, uint64_t, uint32_t> field_bytes,
+    std::conditional_t<WIN, uint64_t, uint32_t> coef_bytes, weights wt, int t0, int nt,
     int first_centre, int XO, int gx, int zchunk, int gz, int ntiles) {
     constexpr int R = kind_traits<KIND>::R;
     constexpr int K = kind_traits<KIND>::K;
@@ -125,27 +126,53 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const int lane = threadIdx.x & 63;
     const int wvu = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 
-    // Tile corner (x0 - RL, y_c - RH - R); all offsets are relative to the
-    // padded origin of the fields: row part (y+h)*sy + (x+h), plane part (z+h)*sz.
+    // Tile corner (x0 - RL, y_c - RH - R).  Offsets are bytes from the
+    // buffers' bases: row part (y+h)*sy + (x+h), plane part (z-zw)*sz.  Fields
+    // below 2 GiB are based at their padded origin (zw = -h); larger ones
+    // (WIN) at plane zw of the workgroup's window, below every plane its
+    // z-chunk touches (at most R(L+2) below z0), which the host keeps below
+    // 2^31 bytes.
     const int ybase = yc - R * H - R;
     const int xbase = x0 - R * L;
-    const rsrc_t rFT = make_rsrc(ftop_o, field_bytes);
-    const rsrc_t rFS = make_rsrc(fsub_o, field_bytes);
-    const rsrc_t rNT = make_rsrc(ftop_n, field_bytes);
-    const rsrc_t rNS = make_rsrc(fsub_n, field_bytes);
+    const int zw = WIN ? max(z0 - R * (L + 2), -hh) : -hh;
+    // window start in bytes of a field and of a coefficient array (0 if !WIN)
+    const uint64_t wfb = WIN ? (uint64_t)(zw + hh) * (uint64_t)sz * 4u : 0u;
+    const uint64_t wcb = WIN ? (uint64_t)(zw + hh) * (uint64_t)sz * CB : 0u;
+    // bytes from the window start to the end of the array, at most 2^31 - 1
+    // (offsets at or beyond kNone stay outside)
+    auto nrec = [](uint64_t total, uint64_t off) -> uint32_t {
+        const uint64_t r = total > off ? total - off : 0u;
+        return (uint32_t)(r < 0x7fffffffull ? r : 0x7fffffffull);
+    };
+    auto buf = [&](const void* p) -> rsrc_t {
+        if constexpr (WIN)
+            return make_rsrc(static_cast<const char*>(p) + wfb, nrec(field_bytes, wfb));
+        else
+            return make_rsrc(p, field_bytes);
+    };
+    const rsrc_t rFT = buf(ftop_o);
+    const rsrc_t rFS = buf(fsub_o);
+    const rsrc_t rNT = buf(ftop_n);
+    const rsrc_t rNS = buf(fsub_n);
     const uint32_t sz4 = (uint32_t)(sz * 4);
     const uint32_t szc = (uint32_t)(sz * CB);
-    auto pf = [&](int z) { return (uint32_t)(z + hh) * sz4; };  // field plane bytes
-    auto pc_ = [&](int z) { return (uint32_t)(z + hh) * szc; };  // coefficient plane bytes
+    // field / coefficient plane bytes
+    auto pf = [&](int z) { return WIN ? (uint32_t)(z - zw) * sz4 : (uint32_t)(z + hh) * sz4; };
+    auto pc_ = [&](int z) { return WIN ? (uint32_t)(z - zw) * szc : (uint32_t)(z + hh) * szc; };
     auto crs = [&](int k) -> coef_rsrc {
+        const uint64_t nrc = WIN ? nrec(coef_bytes, wcb) : (uint64_t)coef_bytes;
         if constexpr (CB == 2) {
-            const uintptr_t a = reinterpret_cast<uintptr_t>(coef + (int64_t)k * sk);
+            const uintptr_t a = reinterpret_cast<uintptr_t>(coef + (int64_t)k * sk) + wcb;
             const uint32_t mis = (uint32_t)(a & 2u);
-            // every word that holds an element; never beyond 2^31 (kNone stays out)
-            const uint64_t nr = (uint64_t)coef_bytes + mis + 2u;
+            // every word that holds an element of the window
+            const uint64_t nr = nrc + mis + 2u;
             return {make_rsrc(reinterpret_cast<const void*>(a - mis),
-                              (uint32_t)(nr < 0x80000000ull ? nr : 0x80000000ull)),
+                              (uint32_t)(nr < 0x7fffffffull ? nr : 0x7fffffffull)),
                     mis};
+        } else if constexpr (WIN) {
+            return {make_rsrc(reinterpret_cast<const char*>(coef + (int64_t)k * sk) + wcb,
+                              (uint32_t)nrc),
+                    0u};
         } else {
             return {make_rsrc(coef + (int64_t)k * sk, coef_bytes), 0u};
         }
@@ -460,10 +487,21 @@ hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
     weights wt;
     for (int i = 0; i < 5; ++i) wt.w[i] = a.wt.w[i];
     wt.alpha = a.wt.alpha;
-    hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD>), dim3(ntiles),
+    // per-workgroup address windows only where a buffer reaches 2 GiB
+    const bool win = a.field_bytes >= 0x80000000ull || a.coef_bytes >= 0x80000000ull;
+    if (win) {
+        hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, true>),
+                           dim3(ntiles), dim3(NWV * 64), 0, s, a.ftop_o, a.fsub_o, a.ftop_n,
+                           a.fsub_n, static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz,
+                           a.d.h, a.d.sy, a.d.sz, a.field_bytes, a.coef_bytes, wt, (int)a.t0,
+                           (int)a.nt, a.first_centre, a.xo, a.gx, a.zchunk, a.gz, ntiles);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, false>), dim3(ntiles),
                        dim3(NWV * 64), 0, s, a.ftop_o, a.fsub_o, a.ftop_n, a.fsub_n,
                        static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.h, a.d.sy,
-                       a.d.sz, a.field_bytes, a.coef_bytes, wt, (int)a.t0, (int)a.nt,
+                       a.d.sz, (uint32_t)a.field_bytes, (uint32_t)a.coef_bytes, wt, (int)a.t0,
+                       (int)a.nt,
                        a.first_centre, a.xo, a.gx, a.zchunk, a.gz, ntiles);
     return hipGetLastError();
 }
