@@ -54,9 +54,10 @@ using ic = std::integral_constant<int, N>;
 
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
-// Byte offset beyond every buffer the kernel touches (fields stay below
-// 2 GiB): a buffer load there returns 0 and a buffer store is dropped, so an
-// operand a row does not need costs neither a branch nor a memory access.
+// Byte offset beyond every buffer the kernel touches (every buffer is sized
+// below 2^31 bytes): a buffer load there returns 0 and a buffer store is
+// dropped, so an operand a row does not need costs neither a branch nor a
+// memory access.
 constexpr uint32_t kNone = 0x80000000u;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
