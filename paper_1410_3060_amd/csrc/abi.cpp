@@ -331,6 +331,17 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
     const int gx = (g->nx + xomax - 1) / xomax;
     const int xo = (g->nx + gx - 1) / gx;
     const bool bf16 = c->dtype == STENCIL_BF16;
+    // workgroups of the row kernel the device holds at once, for the z-chunk
+    long long slots = 0;
+    if (ctx->tuning.zchunk <= 0) {
+        stn::blocked_row_args q;
+        q.dw = dw;
+        q.field_bytes = fbytes;
+        q.coef_bytes = FL.span * (bf16 ? 2 : 4);
+        q.slots_out = &slots;
+        e = stn::launch_blocked_row(kind, bf16, q, ctx->stream);
+        if (e != hipSuccess) return dev_fail(e, "blocked occupancy query");
+    }
     for (const stn::diamond_row& row : plan.rows) {
         stn::blocked_row_args a;
         a.ftop_o = rt;
@@ -352,12 +363,10 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         a.gx = gx;
         int zc = ctx->tuning.zchunk;
         if (zc <= 0) {
-            // about two workgroups per CU, chunks no thinner than 2RL planes
-            const long long per = (long long)row.n_diamonds * gx;
-            long long gz = (512 + per - 1) / per;
-            const long long zmin = std::max(8, 2 * R * L);
-            gz = std::max(1LL, std::min(gz, (long long)g->nz / zmin));
-            zc = (int)((g->nz + gz - 1) / gz);
+            // the chunk count that minimises rounds of resident workgroups x
+            // steps per workgroup (its chunk plus the 2RL steps that fill and
+            // drain the wavefront)
+            zc = stn::pick_zchunk(g->nz, (long long)row.n_diamonds * gx, slots, R * L);
         }
         zc = (int)std::min<int64_t>(zc, zmax);
         a.zchunk = zc;

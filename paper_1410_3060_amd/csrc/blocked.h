@@ -31,6 +31,9 @@ struct blocked_row_args {
     uint64_t coef_bytes;   // bytes of one coefficient array from its padded origin
     // (a workgroup addresses a window of zchunk + 2R(L+1) + 1 planes from a
     // base of its own with 32-bit offsets: the window must stay below 2^31 bytes)
+    // If set, launch_blocked_row launches nothing and stores the number of
+    // workgroups of the kernel it would launch that the device holds at once.
+    long long* slots_out = nullptr;
 };
 
 bool blocked_supported(int kind, int dw);

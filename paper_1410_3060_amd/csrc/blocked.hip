@@ -483,13 +483,22 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
 template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING = false, bool G0 = false,
           int PD = 2>
 hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
+    // per-workgroup address windows only where a buffer reaches 2 GiB
+    const bool win = a.field_bytes >= 0x80000000ull || a.coef_bytes >= 0x80000000ull;
+    if (a.slots_out) {
+        const void* k =
+            win ? reinterpret_cast<const void*>(
+                      &blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, true>)
+                : reinterpret_cast<const void*>(
+                      &blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, false>);
+        *a.slots_out = device_slots(k, NWV * 64);
+        return hipSuccess;
+    }
     const int ntiles = a.n_diamonds * a.gx * a.gz;
     if (ntiles <= 0) return hipSuccess;
     weights wt;
     for (int i = 0; i < 5; ++i) wt.w[i] = a.wt.w[i];
     wt.alpha = a.wt.alpha;
-    // per-workgroup address windows only where a buffer reaches 2 GiB
-    const bool win = a.field_bytes >= 0x80000000ull || a.coef_bytes >= 0x80000000ull;
     if (win) {
         hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, true>),
                            dim3(ntiles), dim3(NWV * 64), 0, s, a.ftop_o, a.fsub_o, a.ftop_n,
