@@ -561,9 +561,10 @@ bool blocked_supported(int kind, int dw) {
     return R == 1 ? (H >= 2 && H <= 6) : (H == 2);
 }
 
-// measured on MI355X: 6 for the 7-point variable-coefficient stencil (512^3),
-// 4 for the constant one (64^3), the only width provided for radius 4
-int blocked_default_dw(int kind) { return kind == 1 ? 4 : (kind == 2 ? 6 : 16); }
+// measured on MI355X over cubes of 64 .. 512: 6 for both 7-point stencils
+// (best or within 10 % of the best at every size), the only width provided
+// for radius 4
+int blocked_default_dw(int kind) { return (kind == 1 || kind == 2) ? 6 : 16; }
 
 int blocked_max_xo(int kind, int dw) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;
