@@ -142,7 +142,11 @@ int stencil_create(stencil_ctx** out, stencil_scheme scheme, const stencil_tunin
    level is recorded and the sweeps write straight into the recording (the
    naive sweep is used whatever the scheme); the buffers then also receive
    the level-0 shell, as with STENCIL_BLOCKED, and for kinds 2-3 the buffer
-   that does not hold level nt is left unspecified. */
+   that does not hold level nt is left unspecified.
+   Graphs: once the context has run the same sizes eagerly (its workspace then
+   exists), a run without recording makes only kernel launches and
+   device-to-device copies on the context's stream, so it can be captured
+   into a HIP graph and replayed. */
 int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
                 const stencil_coeffs* coeffs, int64_t nt, int* result_slot);
 

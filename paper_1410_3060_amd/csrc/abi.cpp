@@ -204,7 +204,12 @@ int set_device(stencil_ctx* ctx) {
         ctx->device = dev;
         return STENCIL_OK;
     }
-    hipError_t e = hipSetDevice(ctx->device);
+    // switch only when needed: a run captured into a HIP graph then makes
+    // no call besides its launches and copies
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur == ctx->device) return STENCIL_OK;
+    e = hipSetDevice(ctx->device);
     return e == hipSuccess ? STENCIL_OK : dev_fail(e, "hipSetDevice");
 }
 
