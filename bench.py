@@ -283,10 +283,13 @@ def scheme_leg(st, workloads, model, torch, np, stream, index, reps=3):
     b0 = st.alloc_field(wl.n3, h)
     cf = st.alloc_field(wl.n3, h, count=wl.coef.shape[0])
     cf.copy_(torch.from_numpy(wl.coef))
+    cf16 = st.alloc_field(wl.n3, h, count=wl.coef.shape[0], dtype=torch.bfloat16)
+    cf16.copy_(torch.from_numpy(workloads.to_bf16_bits(wl.coef).view(np.int16)).view(torch.bfloat16))
     a, b = st.field_like(a0, h), st.field_like(b0, h)
     dw = st.default_dw(kind)
     out = {"workload": wl.name, "dw": dw}
-    for scheme, name in ((st.NAIVE, "naive"), (st.BLOCKED, "blocked")):
+
+    def timed_run(scheme, coef):
         ctx = st.Context(scheme, stream=stream)
         ts = []
         for i in range(reps + 1):
@@ -295,18 +298,25 @@ def scheme_leg(st, workloads, model, torch, np, stream, index, reps=3):
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            ctx.run(kind, a, b, wl.nt, halo=h, coef=cf)
+            ctx.run(kind, a, b, wl.nt, halo=h, coef=coef)
             e1.record(stream)
             torch.cuda.synchronize()
             if i:
                 ts.append(e0.elapsed_time(e1) / 1e3)
         ctx.close()
-        t = float(np.median(ts))
+        return float(np.median(ts))
+
+    for scheme, name in ((st.NAIVE, "naive"), (st.BLOCKED, "blocked")):
+        t = timed_run(scheme, cf)
         bpl = model.naive_code_balance(kind) if scheme == st.NAIVE else \
             model.blocked_bytes_per_lup(kind, dw)
         out[name] = {"glups": round(wl.lups / t / 1e9, 2), "bytes_per_lup": round(bpl, 3),
                      "algorithmic_GBps": round(bpl * wl.lups / t / 1e9, 1)}
     out["blocked_over_naive"] = round(out["blocked"]["glups"] / out["naive"]["glups"], 3)
+    tn, tb = timed_run(st.NAIVE, cf16), timed_run(st.BLOCKED, cf16)
+    out["bf16"] = {"naive_glups": round(wl.lups / tn / 1e9, 2),
+                   "blocked_glups": round(wl.lups / tb / 1e9, 2),
+                   "blocked_over_naive": round(tn / tb, 3)}
     return out
 
 

@@ -69,11 +69,11 @@ __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
 __device__ __forceinline__ void bstore(rsrc_t r, float v, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
 }
-// Coefficient array k as a buffer.  BF16 arrays are read a 32-bit word at a
-// time (the compiler waits for every 16-bit buffer load at once, which would
-// serialise a level's K loads): the resource starts at the word-aligned
-// address at or below the array and `mis` (0 or 2 bytes) is the array's
-// offset from it.
+// Coefficient array k as a buffer.  In a level's update BF16 arrays are read
+// a 32-bit word at a time (the compiler waits for every 16-bit buffer load at
+// once, which would serialise the level's K loads); the resource starts at the
+// word-aligned address at or below the array and `mis` (0 or 2 bytes) is the
+// array's offset from it.
 struct coef_rsrc {
     rsrc_t r;
     uint32_t mis;
@@ -82,6 +82,18 @@ struct coef_rsrc {
 __device__ __forceinline__ float cload(const float*, const coef_rsrc& c, uint32_t voff,
                                        uint32_t soff) {
     return bload(c.r, voff, soff);
+}
+// (prefetched coefficients, read steps before their use, take 16-bit loads;
+// coefficients read in a level's update take the word loads below)
+__device__ __forceinline__ float cload_early(const float*, const coef_rsrc& c, uint32_t voff,
+                                             uint32_t soff) {
+    return bload(c.r, voff, soff);
+}
+__device__ __forceinline__ float cload_early(const uint16_t*, const coef_rsrc& c, uint32_t voff,
+                                             uint32_t soff) {
+    const uint32_t vo = voff >= kNone ? voff : voff + c.mis;
+    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(c.r, vo, soff, 0))
+                           << 16);
 }
 __device__ __forceinline__ float cload(const uint16_t*, const coef_rsrc& c, uint32_t voff,
                                        uint32_t soff) {
@@ -294,7 +306,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                                  s >= z0 - R * (L - 1) && s < z1 + R * (L - 1);
 #pragma unroll
                 for (int k = 0; k < KR; ++k)
-                    pc[SL][c][k] = cload(coef, crs(k), okc ? vc[c] : kNone, okc ? pc_(s) : 0u);
+                    pc[SL][c][k] = cload_early(coef, crs(k), okc ? vc[c] : kNone, okc ? pc_(s) : 0u);
             }
         }
     };
