@@ -140,9 +140,9 @@ int stencil_create(stencil_ctx** out, stencil_scheme scheme, const stencil_tunin
    (u_n; for kind 5 the pair (u_{n-1}, u_n)) for a later stencil_adjoint();
    the recording is replaced by the next recording run.  With k = 1 every
    level is recorded and the sweeps write straight into the recording (the
-   naive sweep is used whatever the scheme); the buffers then also receive
-   the level-0 shell, as with STENCIL_BLOCKED, and for kinds 2-3 the buffer
-   that does not hold level nt is left unspecified.
+   naive sweep is used whatever the scheme); for kind 5 the buffer of u_{nt-1}
+   then receives a copy of it with the level-0 shell, and for kinds 2-3 the
+   buffer that does not hold level nt is left unspecified.
    Graphs: once the context has run the same sizes eagerly (its workspace then
    exists), a run without recording makes only kernel launches and
    device-to-device copies on the context's stream, so it can be captured
