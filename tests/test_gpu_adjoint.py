@@ -88,7 +88,8 @@ def test_adjoint_schedule_is_bitwise_invariant():
     nt = 15
     wl = workloads.make(5, n=N3, nt=nt)
     ref = grads_gpu(wl, nt, k=4)
-    for kw in (dict(k=1), dict(k=1, record=False), dict(k=7), dict(k=15), dict(k=4, record=False),
+    for kw in (dict(k=1), dict(k=1, record=False), dict(k=1, scheme=st.BLOCKED), dict(k=7),
+               dict(k=15), dict(k=4, record=False),
                dict(k=5, scheme=st.BLOCKED), dict(k=3, scheme=st.BLOCKED, record=False)):
         got = grads_gpu(wl, nt, **kw)
         for a, b, name in zip(got[:2], ref[:2], ("um1", "u0")):

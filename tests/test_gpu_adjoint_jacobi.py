@@ -109,7 +109,8 @@ def test_adjoint_jacobi_schedule_invariance(kind):
     wl = workloads.make(WL[kind], n=(70, 33, 21), nt=nt)
     s = seed_field(wl, 2)
     ref0, refc = grads_gpu(wl, nt, s, k=4)
-    for kw in (dict(k=1), dict(k=1, record=False), dict(k=6), dict(k=11), dict(k=3, record=False),
+    for kw in (dict(k=1), dict(k=1, record=False), dict(k=1, scheme=st.BLOCKED), dict(k=6),
+               dict(k=11), dict(k=3, record=False),
                dict(k=5, scheme=st.BLOCKED), dict(k=2, scheme=st.BLOCKED, record=False)):
         g0, gc = grads_gpu(wl, nt, s, **kw)
         assert np.array_equal(g0, ref0), kw
