@@ -22,6 +22,19 @@ from . import (BLOCKED, KIND_7PT_VAR, KIND_25PT_VAR, KIND_25PT_WAVE_VARC, L8_WEI
                Context, alloc_field)
 
 
+def _default_k(nt, ckpt_every, field):
+    """Checkpoint interval: the caller's, else every level when the nt + 1
+    recorded fields take at most half of the free device memory (the adjoint
+    then recomputes nothing), else about sqrt(nt)."""
+    if ckpt_every > 0:
+        return ckpt_every
+    free, _ = torch.cuda.mem_get_info(field.device)
+    nbytes = field.untyped_storage().nbytes()
+    if (nt + 1) * nbytes <= free // 2:
+        return 1
+    return max(1, int(round(math.sqrt(max(nt, 1)))))
+
+
 def _aligned_copy(t, halo):
     pz, py, px = t.shape[-3:]
     out = alloc_field((px - 2 * halo, py - 2 * halo, pz - 2 * halo), halo)
@@ -34,7 +47,7 @@ class WaveFunction(torch.autograd.Function):
     def forward(ctx, u_prev, u0, c, nt: int, halo: int, ckpt_every: int, scheme: int):
         if not (u_prev.is_cuda and u0.is_cuda and c.is_cuda):
             raise ValueError("wave_varc needs CUDA tensors")
-        k = ckpt_every if ckpt_every > 0 else max(1, int(round(math.sqrt(max(nt, 1)))))
+        k = _default_k(nt, ckpt_every, u0)
         a = _aligned_copy(u_prev.detach().float(), halo)
         b = _aligned_copy(u0.detach().float(), halo)
         cc = _aligned_copy(c.detach().float(), halo)
@@ -81,14 +94,12 @@ def wave_varc(u_prev, u0, c, nt: int, *, halo: int = 4, ckpt_every: int = 0,
     Fields are (nz+2h, ny+2h, nx+2h) CUDA tensors (padded, x fastest).  Pass
     the same tensor as u_prev and u0 for a start from rest; autograd then adds
     the two gradients.  ``scheme`` is NAIVE or BLOCKED for the forward.
+    ``ckpt_every`` = 0 records every level when that takes at most half of the
+    free device memory, else every ~sqrt(nt) steps.
     """
     if scheme not in (NAIVE, BLOCKED):
         raise ValueError("scheme must be NAIVE or BLOCKED")
     return WaveFunction.apply(u_prev, u0, c, int(nt), int(halo), int(ckpt_every), int(scheme))
-
-
-def _default_k(nt, ckpt_every):
-    return ckpt_every if ckpt_every > 0 else max(1, int(round(math.sqrt(max(nt, 1)))))
 
 
 class JacobiFunction(torch.autograd.Function):
@@ -104,7 +115,7 @@ class JacobiFunction(torch.autograd.Function):
         cdt = torch.bfloat16 if coef.dtype == torch.bfloat16 else torch.float32
         cf = alloc_field(n3, halo, count=K, dtype=cdt)
         cf.copy_(coef.detach().to(cdt))
-        sctx = Context(scheme, ckpt_every=_default_k(nt, ckpt_every))
+        sctx = Context(scheme, ckpt_every=_default_k(nt, ckpt_every, u0))
         slot = sctx.run(kind, a, b, nt, halo=halo, coef=cf)
         out = (a, b)[slot].clone().reshape(u0.shape)
         ctx.sctx, ctx.nt, ctx.kind, ctx.halo, ctx.cf, ctx.n3 = sctx, nt, kind, halo, cf, n3
@@ -139,7 +150,7 @@ def jacobi_var(u0, coef, nt: int, *, kind: int, halo: int = 0, ckpt_every: int =
     u0 is a (nz+2h, ny+2h, nx+2h) CUDA tensor, coef (K, nz+2h, ny+2h, nx+2h)
     float32 or bfloat16 (BF16 is differentiated at its FP32 expansion; the
     gradient is returned in the coefficients' dtype).  halo defaults to the
-    stencil radius.
+    stencil radius; ``ckpt_every`` as for ``wave_varc``.
     """
     if kind not in (KIND_7PT_VAR, KIND_25PT_VAR):
         raise ValueError("kind must be 2 or 3")
