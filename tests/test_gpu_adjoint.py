@@ -154,3 +154,23 @@ def test_autograd_function_matches_adjoint():
                                   oracle.interior(g0, h))
     np.testing.assert_allclose(oracle.interior(c.grad.double().cpu().numpy(), h),
                                oracle.interior(gc, h), rtol=1e-6, atol=0)
+
+
+def test_autograd_default_records_every_level():
+    """ckpt_every = 0 on a small grid records every level: the gradients equal
+    those of an explicit interval of 1, bit for bit."""
+    import torch
+    from paper_1410_3060_amd.autograd import wave_varc
+    nt = 6
+    wl = workloads.make(5, n=(40, 27, 19), nt=nt)
+    h = wl.halo
+    grads = []
+    for k in (0, 1):
+        up = torch.from_numpy(wl.u_prev).cuda().requires_grad_(True)
+        u0 = torch.from_numpy(wl.u0).cuda().requires_grad_(True)
+        c = torch.from_numpy(wl.coef[0]).cuda().requires_grad_(True)
+        uT = wave_varc(up, u0, c, nt, halo=h, ckpt_every=k)
+        (uT * torch.from_numpy(wl.target).cuda()).sum().backward()
+        grads.append((up.grad.clone(), u0.grad.clone(), c.grad.clone()))
+    for a, b in zip(*grads):
+        assert torch.equal(a, b)
