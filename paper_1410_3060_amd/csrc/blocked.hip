@@ -553,7 +553,13 @@ hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
     } else if constexpr (KIND == 4) {
         if (H == 2) return launch_cfg<KIND, CT, 2, 16, 1, false, true, 1>(a, s);
     } else {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, false, 2>(a, s);
+        // FP32: level 0 from the frontier (fewer registers); BF16: from the
+        // shell ring (without it the compiler serialises the word loads)
+        if constexpr (std::is_same<CT, float>::value) {
+            if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, false, 2>(a, s);
+        } else {
+            if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, true, 2>(a, s);
+        }
     }
     return hipErrorInvalidValue;
 }
