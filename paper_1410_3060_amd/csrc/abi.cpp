@@ -336,6 +336,8 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
     const int gx = (g->nx + xomax - 1) / xomax;
     const int xo = (g->nx + gx - 1) / gx;
     const bool bf16 = c->dtype == STENCIL_BF16;
+    const bool coef_aligned = bf16 && (reinterpret_cast<uintptr_t>(c->arrays) & 3u) == 0 &&
+                              c->sk % 2 == 0 && g->sz % 2 == 0;
     // workgroups of the row kernel the device holds at once, for the z-chunk
     long long slots = 0;
     if (ctx->tuning.zchunk <= 0) {
@@ -344,6 +346,7 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         q.field_bytes = fbytes;
         q.coef_bytes = FL.span * (bf16 ? 2 : 4);
         q.slots_out = &slots;
+        q.coef_aligned = coef_aligned;
         e = stn::launch_blocked_row(kind, bf16, q, ctx->stream);
         if (e != hipSuccess) return dev_fail(e, "blocked occupancy query");
     }
@@ -365,6 +368,7 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         a.field_bytes = fbytes;
         a.coef_bytes = FL.span * (bf16 ? 2 : 4);
         a.xo = xo;
+        a.coef_aligned = coef_aligned;
         a.gx = gx;
         int zc = ctx->tuning.zchunk;
         if (zc <= 0) {

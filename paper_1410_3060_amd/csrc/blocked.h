@@ -34,6 +34,10 @@ struct blocked_row_args {
     // If set, launch_blocked_row launches nothing and stores the number of
     // workgroups of the kernel it would launch that the device holds at once.
     long long* slots_out = nullptr;
+    // BF16 coefficients whose arrays all start on 4-byte boundaries, with even
+    // sk and sz: the level update then reads each element's word at a
+    // per-column offset (ignored for FP32)
+    bool coef_aligned = false;
 };
 
 bool blocked_supported(int kind, int dw);

@@ -105,7 +105,8 @@ __device__ __forceinline__ float cload(const uint16_t*, const coef_rsrc& c, uint
     return __uint_as_float(adj ? (w & 0xffff0000u) : (w << 16));
 }
 
-template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING, bool G0, int PD, bool WIN>
+template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING, bool G0, int PD, bool WIN,
+          bool ALN>
 __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     const float* ftop_o, const float* fsub_o, float* ftop_n, float* fsub_n,
     const CT* __restrict__ coef, int64_t sk, int nx, int ny, int nz, int hh, int64_t sy,
@@ -126,6 +127,9 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     constexpr int KR = CRING ? kslots<KIND> : 1;
     constexpr int NSH = L * R + 1;                   // planes in the shell ring
     constexpr uint32_t CB = sizeof(CT);
+    // ALN: BF16 arrays word-aligned, strides even (the host checks), so an
+    // element's half of its 32-bit word depends on its column only
+    static_assert(!ALN || (CB == 2 && !CRING), "ALN is for BF16 loads in the level update");
     __shared__ float lds[2][L][YT * XT];
 
     const int tile = xcd_remap(blockIdx.x, ntiles);
@@ -200,6 +204,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     int rt[CPT], jo[CPT], jn[CPT];
     bool own[CPT];
     uint32_t vf[CPT], vc[CPT];  // byte offsets of the column's row in a field / coefficient plane
+    uint32_t vw[CPT], vsel[CPT];  // ALN: the column's word offset, byte selector of its half
     int lidx[CPT];              // LDS index of the column
     bool xin[CPT], outx[CPT];
 #pragma unroll
@@ -223,6 +228,10 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         const uint32_t e = rt[c] != 0 ? (uint32_t)((int64_t)(y + hh) * sy + (xc + hh)) : 0u;
         vf[c] = e * 4u;
         vc[c] = e * CB;
+        if constexpr (ALN) {
+            vw[c] = vc[c] & ~3u;
+            vsel[c] = (vc[c] & 2u) ? 0x03020c0cu : 0x01000c0cu;  // high / low half to bits 31..16
+        }
         lidx[c] = valid ? yl * XT + xl : 0;
         xin[c] = x >= 0 && x < nx;
         outx[c] = x >= x0 && x < x0 + XO && x < nx;
@@ -376,8 +385,21 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                                     for (int k = 0; k < K; ++k) Wv[k] = cr[c][jq * R][k];
                                 } else {
                                     const uint32_t so = pc_(z);
+                                    if constexpr (ALN) {
+                                        uint32_t wv[K];
 #pragma unroll
-                                    for (int k = 0; k < K; ++k) Wv[k] = cload(coef, crs(k), vc[c], so);
+                                        for (int k = 0; k < K; ++k)
+                                            wv[k] = __builtin_amdgcn_raw_buffer_load_b32(crs(k).r, vw[c], so, 0);
+                                        // keep the K loads in flight together (otherwise the
+                                        // words share a register and load one at a time)
+                                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                                        for (int k = 0; k < K; ++k)
+                                            Wv[k] = __uint_as_float(__builtin_amdgcn_perm(wv[k], wv[k], vsel[c]));
+                                    } else {
+#pragma unroll
+                                        for (int k = 0; k < K; ++k) Wv[k] = cload(coef, crs(k), vc[c], so);
+                                    }
                                 }
                             }
                             float pv = 0.0f;
@@ -492,18 +514,12 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
         run(ic<0>{});
 }
 
-template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING = false, bool G0 = false,
-          int PD = 2>
-hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
-    // per-workgroup address windows only where a buffer reaches 2 GiB
-    const bool win = a.field_bytes >= 0x80000000ull || a.coef_bytes >= 0x80000000ull;
+template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING, bool G0, int PD, bool WIN,
+          bool ALN>
+hipError_t launch_inst(const blocked_row_args& a, hipStream_t s) {
+    auto kern = blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, WIN, ALN>;
     if (a.slots_out) {
-        const void* k =
-            win ? reinterpret_cast<const void*>(
-                      &blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, true>)
-                : reinterpret_cast<const void*>(
-                      &blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, false>);
-        *a.slots_out = device_slots(k, NWV * 64);
+        *a.slots_out = device_slots(reinterpret_cast<const void*>(kern), NWV * 64);
         return hipSuccess;
     }
     const int ntiles = a.n_diamonds * a.gx * a.gz;
@@ -511,21 +527,26 @@ hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
     weights wt;
     for (int i = 0; i < 5; ++i) wt.w[i] = a.wt.w[i];
     wt.alpha = a.wt.alpha;
-    if (win) {
-        hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, true>),
-                           dim3(ntiles), dim3(NWV * 64), 0, s, a.ftop_o, a.fsub_o, a.ftop_n,
-                           a.fsub_n, static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz,
-                           a.d.h, a.d.sy, a.d.sz, a.field_bytes, a.coef_bytes, wt, (int)a.t0,
-                           (int)a.nt, a.first_centre, a.xo, a.gx, a.zchunk, a.gz, ntiles);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL((blocked_row_kernel<KIND, CT, H, NWV, XCH, CRING, G0, PD, false>), dim3(ntiles),
-                       dim3(NWV * 64), 0, s, a.ftop_o, a.fsub_o, a.ftop_n, a.fsub_n,
-                       static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.h, a.d.sy,
-                       a.d.sz, (uint32_t)a.field_bytes, (uint32_t)a.coef_bytes, wt, (int)a.t0,
-                       (int)a.nt,
-                       a.first_centre, a.xo, a.gx, a.zchunk, a.gz, ntiles);
+    using bytes_t = std::conditional_t<WIN, uint64_t, uint32_t>;
+    hipLaunchKernelGGL(kern, dim3(ntiles), dim3(NWV * 64), 0, s, a.ftop_o, a.fsub_o, a.ftop_n,
+                       a.fsub_n, static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.h,
+                       a.d.sy, a.d.sz, (bytes_t)a.field_bytes, (bytes_t)a.coef_bytes, wt, (int)a.t0,
+                       (int)a.nt, a.first_centre, a.xo, a.gx, a.zchunk, a.gz, ntiles);
     return hipGetLastError();
+}
+
+template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING = false, bool G0 = false,
+          int PD = 2>
+hipError_t launch_cfg(const blocked_row_args& a, hipStream_t s) {
+    // per-workgroup address windows only where a buffer reaches 2 GiB
+    const bool win = a.field_bytes >= 0x80000000ull || a.coef_bytes >= 0x80000000ull;
+    if constexpr (std::is_same<CT, uint16_t>::value && !CRING) {
+        if (a.coef_aligned)
+            return win ? launch_inst<KIND, CT, H, NWV, XCH, CRING, G0, PD, true, true>(a, s)
+                       : launch_inst<KIND, CT, H, NWV, XCH, CRING, G0, PD, false, true>(a, s);
+    }
+    return win ? launch_inst<KIND, CT, H, NWV, XCH, CRING, G0, PD, true, false>(a, s)
+               : launch_inst<KIND, CT, H, NWV, XCH, CRING, G0, PD, false, false>(a, s);
 }
 
 // Workgroup shape per (kind, H): waves, 64-lane x chunks, coefficient ring,

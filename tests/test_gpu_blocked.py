@@ -13,7 +13,7 @@ import pytest
 import paper_1410_3060_amd as st
 import workloads
 
-from gpu_util import max_rel, rel_l2, run_gpu, run_oracle
+from gpu_util import coef_to_dev, from_dev, gpu_weights, max_rel, rel_l2, run_gpu, run_oracle, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +82,36 @@ def test_blocked_contiguous_layout(index):
     nb, _ = run_gpu(wl, st.NAIVE, aligned=False)
     bl, _ = run_gpu(wl, st.BLOCKED, aligned=False, dw=DWS[index][0])
     assert_bitwise(bl, nb, f"workload {index} contiguous")
+
+
+@pytest.mark.parametrize("index", [4, 5])
+def test_blocked_bf16_unaligned_coefficients(index):
+    """BF16 coefficient arrays that do not all start on 4-byte boundaries
+    (odd plane and array strides of a contiguous layout, and a base 2 bytes
+    past an allocation) take the general word-select loads; aligned arrays
+    take the per-column selector.  All three equal the naive scheme bit for
+    bit."""
+    import torch
+    wl = workloads.make(index, n=(77, 51, 33), nt=6, coef_dtype="bf16")
+    h = wl.halo
+    assert ((77 + 2 * h) * (51 + 2 * h)) % 2 == 1  # odd sz and sk
+    ref, _ = run_gpu(wl, st.NAIVE)
+    outs = {"aligned": run_gpu(wl, st.BLOCKED, dw=16)[0],
+            "contiguous": run_gpu(wl, st.BLOCKED, aligned=False, dw=16)[0]}
+    # the same arrays 2 bytes past a 256-byte aligned allocation
+    cf = coef_to_dev(wl, aligned=False)
+    buf = torch.empty(cf.numel() + 1, dtype=cf.dtype, device="cuda")
+    shifted = buf[1:].view(cf.shape)
+    shifted.copy_(cf)
+    assert shifted.data_ptr() % 4 == 2
+    a = to_dev(wl.u_prev if index == 5 else wl.u0, h, False)
+    b = to_dev(wl.u0 if index == 5 else np.zeros_like(wl.u0), h, False)
+    with st.Context(st.BLOCKED, dw=16) as ctx:
+        slot = ctx.run(wl.kind, a, b, 6, halo=h, coef=shifted, w=gpu_weights(wl), alpha=wl.alpha)
+        ctx.sync()
+    outs["shifted base"] = from_dev((a, b)[slot])
+    for what, got in outs.items():
+        assert_bitwise(got, ref, f"workload {index} bf16 {what}")
 
 
 def test_blocked_thin_and_tiny():
