@@ -84,20 +84,21 @@ def test_blocked_contiguous_layout(index):
     assert_bitwise(bl, nb, f"workload {index} contiguous")
 
 
-@pytest.mark.parametrize("index", [4, 5])
+@pytest.mark.parametrize("index", [3, 4, 5])
 def test_blocked_bf16_unaligned_coefficients(index):
     """BF16 coefficient arrays that do not all start on 4-byte boundaries
     (odd plane and array strides of a contiguous layout, and a base 2 bytes
-    past an allocation) take the general word-select loads; aligned arrays
-    take the per-column selector.  All three equal the naive scheme bit for
+    past an allocation) take the general loads; aligned arrays of the 25-point
+    and leapfrog kinds take word loads and a per-column selector.  All three equal the naive scheme bit for
     bit."""
     import torch
     wl = workloads.make(index, n=(77, 51, 33), nt=6, coef_dtype="bf16")
     h = wl.halo
     assert ((77 + 2 * h) * (51 + 2 * h)) % 2 == 1  # odd sz and sk
+    dw = DWS[index][0]
     ref, _ = run_gpu(wl, st.NAIVE)
-    outs = {"aligned": run_gpu(wl, st.BLOCKED, dw=16)[0],
-            "contiguous": run_gpu(wl, st.BLOCKED, aligned=False, dw=16)[0]}
+    outs = {"aligned": run_gpu(wl, st.BLOCKED, dw=dw)[0],
+            "contiguous": run_gpu(wl, st.BLOCKED, aligned=False, dw=dw)[0]}
     # the same arrays 2 bytes past a 256-byte aligned allocation
     cf = coef_to_dev(wl, aligned=False)
     buf = torch.empty(cf.numel() + 1, dtype=cf.dtype, device="cuda")
@@ -106,7 +107,7 @@ def test_blocked_bf16_unaligned_coefficients(index):
     assert shifted.data_ptr() % 4 == 2
     a = to_dev(wl.u_prev if index == 5 else wl.u0, h, False)
     b = to_dev(wl.u0 if index == 5 else np.zeros_like(wl.u0), h, False)
-    with st.Context(st.BLOCKED, dw=16) as ctx:
+    with st.Context(st.BLOCKED, dw=dw) as ctx:
         slot = ctx.run(wl.kind, a, b, 6, halo=h, coef=shifted, w=gpu_weights(wl), alpha=wl.alpha)
         ctx.sync()
     outs["shifted base"] = from_dev((a, b)[slot])
