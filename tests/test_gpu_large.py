@@ -1,6 +1,7 @@
 """Fields larger than 2 GiB: the blocked kernel addresses each z-chunk through
 a window of 32-bit offsets from a base of its own, so it must still equal the
-naive sweep bit for bit (FP32 and BF16 coefficients, radius 1 and 4)."""
+naive sweep bit for bit (FP32 and BF16 coefficients, radius 1 and 4; the
+BF16 cases of radius 4 take the word-aligned coefficient loads)."""
 import pytest
 
 import paper_1410_3060_amd as st
@@ -29,7 +30,9 @@ def inputs(kind, n3, h, coef_dtype):
 
 @pytest.mark.parametrize("kind,n3,nt,coef_dtype", [(2, (1000, 1000, 560), 7, "f32"),
                                                     (2, (1000, 1000, 560), 4, "bf16"),
-                                                    (5, (832, 832, 800), 5, "f32")])
+                                                    (5, (832, 832, 800), 5, "f32"),
+                                                    (3, (832, 832, 800), 3, "bf16"),
+                                                    (5, (832, 832, 800), 4, "bf16")])
 def test_blocked_beyond_2gib(kind, n3, nt, coef_dtype):
     import torch
     h = st.RADIUS[kind]
