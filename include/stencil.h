@@ -39,7 +39,10 @@
  *   (expanded exactly to FP32 in the kernels); arithmetic is FP32 with one
  *   fixed fused-multiply-add order per kind, the same in every scheme, so the
  *   blocked scheme reproduces the naive scheme bit for bit.  FP64 is used only
- *   for the coefficient gradient of stencil_adjoint().
+ *   for the coefficient gradient of stencil_adjoint().  BF16 arrays may start
+ *   on any 2-byte boundary.  Arrays on 4-byte boundaries, with even sk and sz,
+ *   are read faster by the blocked scheme for kinds 3 and 5, with the same
+ *   results.
  * Streams.  Calls are asynchronous on the HIP stream given to stencil_create()
  *   (borrowed, not owned).  Device faults surface at the next stencil_sync().
  * Errors.  Every argument is validated on the host before any HIP call.  A
