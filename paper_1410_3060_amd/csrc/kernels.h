@@ -25,9 +25,7 @@ struct host_weights {
 hipError_t launch_naive_step(int kind, bool coef_bf16, const float* cur, const float* prev,
                              float* out, const void* coef, int64_t sk, const dims& d,
                              const host_weights& wt, int zchunk, hipStream_t s);
-
-// Planes per z-chunk the naive launcher picks when zchunk == 0.
-int naive_default_zchunk(int kind, const dims& d);
+// (zchunk <= 0: planes per z-chunk chosen from the kernel's occupancy)
 
 // Workgroups of `kernel` (with `threads` threads) resident on the current
 // device at once: its occupancy per compute unit times the compute units.

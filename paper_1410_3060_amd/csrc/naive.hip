@@ -173,23 +173,36 @@ __global__ __launch_bounds__(NW * 64) void naive_step_kernel(
 }
 
 // Rows per lane and waves per workgroup (tile 64 x NW*RPT), measured per kind:
-// the radius-4 kinds take 8 or 16 waves (taller tiles re-read fewer halo rows).
-template <int KIND>
+// the radius-4 kinds take 8 or 16 waves (taller tiles re-read fewer halo rows);
+// the 7-point stencil with BF16 coefficients takes one row per lane and 8
+// waves (216 GLUP/s at 512^3 against 148 with the FP32 shape).
+template <int KIND, typename CT>
 constexpr int naive_rpt() {
+    if (KIND == 2 && sizeof(CT) == 2) return 1;
     return KIND == 1 || KIND == 2 ? 8 : (KIND == 4 ? 4 : 1);
 }
-template <int KIND>
+template <int KIND, typename CT>
 constexpr int naive_nw() {
+    if (KIND == 2 && sizeof(CT) == 2) return 8;
     return KIND == 1 || KIND == 2 ? 4 : (KIND == 4 ? 8 : 16);
+}
+// planes per z-chunk from the occupancy of the instance that runs
+template <int KIND, typename CT>
+int zchunk_for(const dims& d) {
+    constexpr int RPT = naive_rpt<KIND, CT>(), NW = naive_nw<KIND, CT>(), TY = NW * RPT;
+    const long long txy = (long long)((d.nx + 63) / 64) * ((d.ny + TY - 1) / TY);
+    const void* k = reinterpret_cast<const void*>(&naive_step_kernel<KIND, CT, RPT, NW>);
+    return pick_zchunk(d.nz, txy, device_slots(k, NW * 64), kind_traits<KIND>::R);
 }
 
 template <int KIND, typename CT>
 hipError_t launch_kind(const float* cur, const float* prev, float* out, const void* coef,
                        int64_t sk, const dims& d, const host_weights& hw, int zchunk,
                        hipStream_t s) {
-    constexpr int RPT = naive_rpt<KIND>();
-    constexpr int NW = naive_nw<KIND>();
+    constexpr int RPT = naive_rpt<KIND, CT>();
+    constexpr int NW = naive_nw<KIND, CT>();
     constexpr int TY = NW * RPT;
+    if (zchunk <= 0) zchunk = zchunk_for<KIND, CT>(d);
     const int gx = (d.nx + 63) / 64, gy = (d.ny + TY - 1) / TY;
     const int gz = (d.nz + zchunk - 1) / zchunk;
     const long long ntiles = (long long)gx * gy * gz;
@@ -304,28 +317,9 @@ int pick_zchunk(int nz, long long txy, long long slots, int R) {
     return best;
 }
 
-template <int KIND>
-int zchunk_for(const dims& d) {
-    constexpr int RPT = naive_rpt<KIND>(), NW = naive_nw<KIND>(), TY = NW * RPT;
-    const long long txy = (long long)((d.nx + 63) / 64) * ((d.ny + TY - 1) / TY);
-    const void* k = reinterpret_cast<const void*>(&naive_step_kernel<KIND, float, RPT, NW>);
-    return pick_zchunk(d.nz, txy, device_slots(k, NW * 64), kind_traits<KIND>::R);
-}
-
-int naive_default_zchunk(int kind, const dims& d) {
-    switch (kind) {
-    case 1: return zchunk_for<1>(d);
-    case 2: return zchunk_for<2>(d);
-    case 3: return zchunk_for<3>(d);
-    case 4: return zchunk_for<4>(d);
-    default: return zchunk_for<5>(d);
-    }
-}
-
 hipError_t launch_naive_step(int kind, bool bf16, const float* cur, const float* prev, float* out,
                              const void* coef, int64_t sk, const dims& d, const host_weights& wt,
                              int zchunk, hipStream_t s) {
-    if (zchunk <= 0) zchunk = naive_default_zchunk(kind, d);
     switch (kind) {
     case 1: return launch_kind<1, float>(cur, prev, out, coef, sk, d, wt, zchunk, s);
     case 2:
