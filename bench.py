@@ -10,12 +10,18 @@ inputs resident in HBM.  value = lattice-site updates per second, counting
 only the algorithmic 480^3 * 100 updates (never recomputed halos).
 
 Beside it the other scheme is timed on the same run, both with BF16
-coefficients; the 7-point variable-coefficient workload (512^3, 100 steps)
-with both schemes; and the adjoints, forward (recording) and backward: the
+coefficients; every other workload at full size with both schemes (7-point
+constant 64^3 x 10, 25-point leapfrog 512^3 x 100, 7-point variable 512^3 x
+100, leapfrog with c(x) 256^3 x 200), each with the error of its level nt
+against the FP64 oracle over the whole interior (for the 25-point
+variable-coefficient workload with BF16 coefficients: against the oracle on
+the BF16-rounded values, and the storage error against the oracle on the
+FP32 values); and the adjoints, forward (recording) and backward: the
 leapfrog with c(x) (256^3, 200 steps; checkpoints every 14 steps and every
 level) and the 7- and 25-point variable-coefficient Jacobi workloads (every
-level recorded).  The FP64 CPU oracle is timed on a bounded sample of the
-same workload on the host cores.
+level recorded).  The FP64 CPU oracle is timed on the full 25-point
+workload on the host cores (its result is the reference of the error above)
+and on the 7-point constant workload in seconds, on all cores and on one.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -167,6 +173,11 @@ def main():
                 "algorithmic_per_launch_GB": round(bpl * lups / n_launch / 1e9, 3),
                 "copy_probe_GBps": probe["GBps"], "kernel": kname,
                 "bytes_per_lup": round(bpl, 3), "avg_launch_ms": round(avg_launch * 1e3, 4)}
+    if traffic is not None:
+        # the rate of the bytes the counters saw (L2 misses), beside the
+        # algorithmic rate that `achieved` reports
+        roofline["traffic_GBps"] = round(traffic / avg_launch / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / avg_launch / 1e9 / PEAK_HBM_GBS, 4)
 
     extras = {}
     if not args.no_extras:
@@ -180,6 +191,16 @@ def main():
                             "algorithmic_GBps": round(b * lups / t / 1e9, 1)}
         extras["blocked_over_naive"] = round(tn_s / tb_s, 3)
         log(f"[bench] naive {extras['naive']['glups']}, blocked {extras['blocked']['glups']} GLUP/s")
+        # level nt of both schemes (FP32 coefficients), for the error legs
+        fin = {}
+        for name, cx in (("naive", ctx_n), ("blocked", ctx_b)):
+            u_a.copy_(init_a)
+            u_b.copy_(init_b)
+            slot = cx.run(kind, u_a, u_b, nt, halo=h, coef=coef32, w=w, alpha=wl.alpha)
+            fin[name] = (u_a, u_b)[slot].cpu().numpy()
+        extras["blocked_equals_naive"] = bool(np.array_equal(fin["naive"], fin["blocked"]))
+        gpu_final = {"f32": fin["blocked"]}
+        del fin
         if wl.coef is not None:
             # BF16 coefficient storage
             coef16 = upload_coef(workloads.to_bf16_bits(wl.coef).view(np.int16), torch.bfloat16)
@@ -189,9 +210,27 @@ def main():
                               "naive_glups": round(lups / tn16 / 1e9, 2),
                               "blocked_over_naive": round(tn16 / tb16, 3)}
             log(f"[bench] bf16: blocked {lups / tb16 / 1e9:.1f}, naive {lups / tn16 / 1e9:.1f} GLUP/s")
-            del coef16
-        if args.workload != 3 and args.n is None:
-            extras["7pt_var"] = scheme_leg(st, workloads, model, torch, np, stream, 3)
+            fin = {}
+            for name, cx in (("naive", ctx_n), ("blocked", ctx_b)):
+                u_a.copy_(init_a)
+                u_b.copy_(init_b)
+                slot = cx.run(kind, u_a, u_b, nt, halo=h, coef=coef16, w=w, alpha=wl.alpha)
+                fin[name] = (u_a, u_b)[slot].cpu().numpy()
+            extras["bf16"]["blocked_equals_naive"] = bool(np.array_equal(fin["naive"],
+                                                                         fin["blocked"]))
+            gpu_final["bf16"] = fin["blocked"]
+            del coef16, fin
+        if args.n is None:
+            configs = {}
+            for i in (1, 2, 3, 5):
+                if i == args.workload:
+                    continue
+                try:
+                    configs[workloads.NAMES[i]] = config_leg(st, workloads, model, torch, np,
+                                                             stream, i, args.cpu_seconds)
+                except Exception as e:  # a failing leg reports, it does not sink the line
+                    configs[workloads.NAMES[i]] = {"error": str(e)[:200]}
+            extras["configs"] = configs
         try:
             extras["adjoint"] = adjoint_leg(st, workloads, torch, np, stream, args)
         except Exception as e:  # the adjoint legs report, they do not sink the line
@@ -207,8 +246,32 @@ def main():
     ctx_n.close()
 
     cpu = None
+    ref = None
     if not args.no_cpu:
-        cpu = cpu_leg(wl, args.cpu_seconds)
+        cpu, ref = cpu_leg(wl, args.cpu_seconds)
+        if args.n is None and not args.no_extras:
+            extras["c1_oracle_seconds"] = c1_oracle_seconds(workloads)
+    if not args.no_extras and args.n is None:
+        # error of level nt against the FP64 oracle over the whole interior
+        err = {}
+        for name, c in extras.get("configs", {}).items():
+            if "error_vs_oracle" in c:
+                err[name] = c["error_vs_oracle"]
+        err[wl.name] = error_stats(np, gpu_final["f32"], ref if ref is not None else
+                                   oracle_final(np, wl, wl.coef), h)
+        if "bf16" in gpu_final:
+            rounded = workloads.bf16_bits_to_f32(workloads.to_bf16_bits(wl.coef))
+            parity = error_stats(np, gpu_final["bf16"], oracle_final(np, wl, rounded), h)
+            del rounded
+            storage = error_stats(np, gpu_final["bf16"], ref if ref is not None else
+                                  oracle_final(np, wl, wl.coef), h)
+            err[wl.name + "-bf16"] = {
+                "vs_oracle_on_bf16_values": parity,
+                "storage_error_vs_oracle_on_f32_values": storage,
+                "storage_target_rel_l2": 1e-3,
+                "storage_target_met": storage["rel_l2"] <= 1e-3}
+        extras["error"] = err
+        log("[bench] error vs FP64 oracle: " + json.dumps(err))
 
     line = {
         "metric": "GLUP/s (%s) + HBM GB/s; blocked vs naive" % wl.name,
@@ -272,52 +335,6 @@ def copy_probe(torch, nbytes=1 << 32, reps=10):
     del a, b
     return {"bytes_per_copy": 2 * nbytes, "GBps": round(2 * nbytes / sec / 1e9, 1),
             "ms": round(sec * 1e3, 3)}
-
-
-def scheme_leg(st, workloads, model, torch, np, stream, index, reps=3):
-    """Naive and blocked GLUP/s of another workload (default diamond width)."""
-    wl = workloads.make(index)
-    h, kind = wl.halo, wl.kind
-    a0 = st.alloc_field(wl.n3, h)
-    a0.copy_(torch.from_numpy(wl.u0))
-    b0 = st.alloc_field(wl.n3, h)
-    cf = st.alloc_field(wl.n3, h, count=wl.coef.shape[0])
-    cf.copy_(torch.from_numpy(wl.coef))
-    cf16 = st.alloc_field(wl.n3, h, count=wl.coef.shape[0], dtype=torch.bfloat16)
-    cf16.copy_(torch.from_numpy(workloads.to_bf16_bits(wl.coef).view(np.int16)).view(torch.bfloat16))
-    a, b = st.field_like(a0, h), st.field_like(b0, h)
-    dw = st.default_dw(kind)
-    out = {"workload": wl.name, "dw": dw}
-
-    def timed_run(scheme, coef):
-        ctx = st.Context(scheme, stream=stream)
-        ts = []
-        for i in range(reps + 1):
-            a.copy_(a0)
-            b.copy_(b0)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ctx.run(kind, a, b, wl.nt, halo=h, coef=coef)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            if i:
-                ts.append(e0.elapsed_time(e1) / 1e3)
-        ctx.close()
-        return float(np.median(ts))
-
-    for scheme, name in ((st.NAIVE, "naive"), (st.BLOCKED, "blocked")):
-        t = timed_run(scheme, cf)
-        bpl = model.naive_code_balance(kind) if scheme == st.NAIVE else \
-            model.blocked_bytes_per_lup(kind, dw)
-        out[name] = {"glups": round(wl.lups / t / 1e9, 2), "bytes_per_lup": round(bpl, 3),
-                     "algorithmic_GBps": round(bpl * wl.lups / t / 1e9, 1)}
-    out["blocked_over_naive"] = round(out["blocked"]["glups"] / out["naive"]["glups"], 3)
-    tn, tb = timed_run(st.NAIVE, cf16), timed_run(st.BLOCKED, cf16)
-    out["bf16"] = {"naive_glups": round(wl.lups / tn / 1e9, 2),
-                   "blocked_glups": round(wl.lups / tb / 1e9, 2),
-                   "blocked_over_naive": round(tn / tb, 3)}
-    return out
 
 
 def timed_pair(torch, stream, first, second):
@@ -479,38 +496,144 @@ def sweep_leg(torch, args):
     return out
 
 
+def error_stats(np, got, want, h):
+    """rel-L2 and max-norm error of a level against the oracle's, interior only."""
+    g = got[h:-h, h:-h, h:-h].astype(np.float64)
+    w = want[h:-h, h:-h, h:-h]
+    d = g - w
+    return {"rel_l2": float(np.linalg.norm(d.ravel()) / np.linalg.norm(w.ravel())),
+            "max_rel": float(np.abs(d).max() / np.abs(w).max())}
+
+
+def oracle_final(np, wl, coef):
+    """The FP64 oracle's level nt of the workload with the given coefficient values."""
+    import oracle
+    h = wl.halo
+    w = wl.w if wl.kind == 1 else (oracle.l8_weights_3d() if wl.kind in (4, 5) else ())
+    cf = None if coef is None else np.asarray(coef, dtype=np.float64)
+    if wl.kind in (4, 5):
+        return oracle.run(wl.kind, wl.u0.astype(np.float64), h, wl.nt,
+                          u_prev=wl.u_prev.astype(np.float64), coef=cf, w=w, alpha=wl.alpha)[1]
+    return oracle.run(wl.kind, wl.u0.astype(np.float64), h, wl.nt, coef=cf, w=w)
+
+
+def config_leg(st, workloads, model, torch, np, stream, index, cpu_seconds, reps=3):
+    """One workload at full size: naive and blocked GLUP/s (default diamond
+    width), whether blocked equals naive bit for bit, and the error of level
+    nt against the FP64 oracle over the whole interior."""
+    wl = workloads.make(index)
+    h, kind, nt = wl.halo, wl.kind, wl.nt
+    lf = kind in (4, 5)
+    w = wl.w if kind == 1 else (st.L8_WEIGHTS if lf else ())
+    a0 = st.alloc_field(wl.n3, h)
+    a0.copy_(torch.from_numpy(wl.u_prev if lf else wl.u0))
+    b0 = st.alloc_field(wl.n3, h)
+    b0.copy_(torch.from_numpy(wl.u0 if lf else np.zeros_like(wl.u0)))
+    cf = None
+    if wl.coef is not None:
+        cf = st.alloc_field(wl.n3, h, count=wl.coef.shape[0])
+        cf.copy_(torch.from_numpy(wl.coef))
+    a, b = st.field_like(a0, h), st.field_like(b0, h)
+    dw = st.default_dw(kind)
+    out = {"workload": wl.name, "dw": dw}
+    fin = {}
+    for scheme, name in ((st.NAIVE, "naive"), (st.BLOCKED, "blocked")):
+        ctx = st.Context(scheme, stream=stream)
+        ts = []
+        for i in range(reps + 1):
+            a.copy_(a0)
+            b.copy_(b0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            slot = ctx.run(kind, a, b, nt, halo=h, coef=cf, w=w, alpha=wl.alpha)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if i:
+                ts.append(e0.elapsed_time(e1) / 1e3)
+        ctx.close()
+        t = float(np.median(ts))
+        fin[name] = (a, b)[slot].cpu().numpy()
+        bpl = model.naive_code_balance(kind) if scheme == st.NAIVE else \
+            model.blocked_bytes_per_lup(kind, dw)
+        out[name] = {"glups": round(wl.lups / t / 1e9, 2), "ms_per_run": round(t * 1e3, 3),
+                     "bytes_per_lup": round(bpl, 3),
+                     "algorithmic_GBps": round(bpl * wl.lups / t / 1e9, 1)}
+    out["blocked_over_naive"] = round(out["blocked"]["glups"] / out["naive"]["glups"], 3)
+    out["blocked_equals_naive"] = bool(np.array_equal(fin["naive"], fin["blocked"]))
+    del a, b, a0, b0, cf
+    torch.cuda.empty_cache()
+    out["error_vs_oracle"] = error_stats(np, fin["blocked"], oracle_final(np, wl, wl.coef), h)
+    log(f"[bench] {wl.name}: naive {out['naive']['glups']}, blocked {out['blocked']['glups']} "
+        f"GLUP/s; error {out['error_vs_oracle']}")
+    return out
+
+
+def c1_oracle_seconds(workloads):
+    """Seconds of the FP64 oracle on the 7-point constant workload (64^3, 10
+    steps), time-step loop only: on all host cores and on one thread."""
+    import numpy as np
+
+    import oracle
+    wl = workloads.make(1)
+    out = {"workload": wl.name}
+    for key, nth in (("all_cores", 0), ("one_thread", 1)):
+        best = None
+        for _ in range(3):
+            t = []
+            oracle.run(1, wl.u0.astype(np.float64), wl.halo, wl.nt, w=wl.w, nthreads=nth,
+                       timing=t)
+            best = t[0] if best is None else min(best, t[0])
+        out[key] = {"seconds": round(best, 5),
+                    "threads": oracle.max_threads() if nth == 0 else 1}
+    return out
+
+
 def cpu_leg(wl, seconds):
     """The FP64 oracle on a bounded sample of the workload, on all host cores.
 
     The sample is the full seeded grid run for as many of the workload's time
     steps as fit in about `seconds` (one calibration step first); if a single
-    step already takes longer, the leading planes of the grid instead."""
+    step already takes longer, the leading planes of the grid instead.
+    Returns the record and, when the sample was the whole run, the oracle's
+    level nt (else None)."""
     import numpy as np
 
     import oracle
     h = wl.halo
     nx, ny, nz = wl.n3
+    lf = wl.kind in (4, 5)
+    w = wl.w if wl.kind == 1 else (oracle.l8_weights_3d() if lf else ())
     u = np.asarray(wl.u0, dtype=np.float64)
-    cf = np.asarray(wl.coef, dtype=np.float64)
+    up = np.asarray(wl.u_prev, dtype=np.float64) if lf else None
+    cf = None if wl.coef is None else np.asarray(wl.coef, dtype=np.float64)
+
+    def run(nsteps, t):
+        r = oracle.run(wl.kind, u, h, nsteps, u_prev=up, coef=cf, w=w, alpha=wl.alpha, timing=t)
+        return r[1] if lf else r
+
     t = []
-    oracle.run(wl.kind, u, h, 1, coef=cf, timing=t)
+    run(1, t)
     per_step = max(t[0], 1e-3)
     nz_s = nz
     if per_step > seconds / 4:
         nz_s = max(2 * h, int(nz * seconds / 4 / per_step))
         sl = slice(0, nz_s + 2 * h)
         u = np.ascontiguousarray(u[sl])
-        cf = np.ascontiguousarray(cf[:, sl])
+        up = None if up is None else np.ascontiguousarray(up[sl])
+        cf = None if cf is None else np.ascontiguousarray(cf[:, sl])
         per_step *= nz_s / nz
     nt_s = int(max(1, min(wl.nt, seconds / per_step)))
     t = []
-    oracle.run(wl.kind, u, h, nt_s, coef=cf, timing=t)
+    res = run(nt_s, t)
     secs = t[0]
     glups = nx * ny * nz_s * nt_s / secs / 1e9
-    return {"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"{nx}x{ny}x{nz_s} of the same seeded grid, {nt_s} of {wl.nt} steps, FP64, "
-                      f"{secs:.1f} s", "host_cpus": os.cpu_count()}
+    full = nz_s == nz and nt_s == wl.nt
+    return ({"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.max_threads(),
+             "kind": "oracle",
+             "sample": f"{nx}x{ny}x{nz_s} of the same seeded grid, {nt_s} of {wl.nt} steps, FP64, "
+                       f"{secs:.1f} s", "host_cpus": os.cpu_count()},
+            res if full else None)
 
 
 if __name__ == "__main__":

@@ -4,7 +4,7 @@
  * Repeated time-stepped updates of 3D star stencils on Cartesian lattices,
  * after Malas et al., "Multicore-optimized wavefront diamond blocking for
  * optimizing stencil updates" (arXiv 1410.3060):
- *   - the five operators of Fig. 1b-1e (Sect. 2.1),
+ *   - the five operators of Fig. 1b-1e (Sect. 3.1),
  *   - a one-sweep-per-step scheme ("naive", Sect. 4.1),
  *   - a temporally blocked scheme: diamond tiles along y with a wavefront
  *     along z (Sect. 4.2-4.3 and 5.1),
@@ -17,7 +17,7 @@
  * Memory.  Every array argument is a DEVICE pointer owned by the caller, who
  *   keeps it alive until stencil_sync() returns.  The library owns only its
  *   context and the workspace inside it.
- * Layout (Sect. 2.1: x is the leading dimension, then y, then z).  A field is
+ * Layout (Sect. 3.1: x is the leading dimension, then y, then z).  A field is
  *   a padded box with a boundary shell of width `halo` on all six faces.  The
  *   pointer addresses the padded origin (x, y, z) = (-halo, -halo, -halo);
  *   interior point (x, y, z), 0 <= x < nx etc., is element
@@ -27,11 +27,10 @@
  *   outputs) share these element strides.
  * Boundary.  The shell is a time-independent Dirichlet boundary: every level
  *   reads the shell of the buffer that holds level 0 (u[0] for kinds 1-3,
- *   u[1] for kinds 4-5).  The naive scheme reads the shell of the buffer that
- *   holds the level it reads, so the two schemes agree when u[0] and u[1]
- *   carry the same shell (the usual case: both zero); the blocked scheme
- *   copies the level-0 shell into the other buffer before it starts.
- * Two-buffer time storage (Sect. 2.1: only two levels are stored and level
+ *   u[1] for kinds 4-5).  Both schemes copy the R-deep level-0 shell into the
+ *   other buffer before the first step (nt >= 1), so they agree bit for bit
+ *   whatever shells the two buffers carried on entry.
+ * Two-buffer time storage (Sect. 3.1: only two levels are stored and level
  *   t+1 overwrites level t-1).  Jacobi kinds (1-3): u[0] holds level 0 on
  *   entry and level t lives in u[t % 2].  Leapfrog kinds (4-5): u[0] holds
  *   u_{-1}, u[1] holds u_0 and level n lives in u[(n + 1) % 2].

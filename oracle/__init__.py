@@ -5,13 +5,13 @@ the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
 code with the GPU library and the library never calls it.
 
 The arithmetic lives in ``oracle.c`` (plain loops, one sweep per time step, in
-double precision; Sect. 2.1 and Fig. 1 of the paper); this module builds it
+double precision; Sect. 3.1 and Fig. 1 of the paper); this module builds it
 with gcc and marshals numpy arrays.  ``weights.py`` derives the 8th-order
 second-derivative weights exactly; ``brute.py`` is an independent
 matrix-power formulation used to pin the loops on tiny grids.
 
 Array convention: every field is a C-contiguous float64 numpy array of shape
-(nz+2h, ny+2h, nx+2h) (x fastest, Sect. 2.1); the h-wide shell is a fixed
+(nz+2h, ny+2h, nx+2h) (x fastest, Sect. 3.1); the h-wide shell is a fixed
 boundary that is read and never written.
 """
 from __future__ import annotations
@@ -137,6 +137,10 @@ def step_points(kind, u, h, pts, *, u_prev=None, coef=None, w=(0.0,) * 5, alpha=
     n = pts.shape[0]
     R = RADIUS[kind]
     nx, ny, nz = _dims(u, h)
+    if h < R or pts.ndim != 2 or pts.shape[1] != 3:
+        raise ValueError("step_points: bad boundary width or point array")
+    if n and ((pts < 0).any() or (pts >= np.array([nx, ny, nz])).any()):
+        raise ValueError("step_points: a point lies outside the interior")
     # gather the (2R+1)^3 neighbourhood boxes into a small padded array per
     # point so that huge float32 fields need not be converted whole
     side = 2 * R + 1

@@ -9,13 +9,13 @@
  * Paper: Malas, Hager, Ltaief, Stengel, Wellein, Keyes, "Multicore-optimized
  * wavefront diamond blocking for optimizing stencil updates" (arXiv 1410.3060).
  *
- * What it computes (Sect. 2.1, Fig. 1b-1e): nt Jacobi-style sweeps, one full
+ * What it computes (Sect. 3.1, Fig. 1b-1e): nt Jacobi-style sweeps, one full
  * sweep per time step, each sweep reading only the previous level(s) and
  * writing a new one.  No temporal blocking, no tiling, no fusion: the
  * temporally blocked schemes of Sect. 4-5 reorder exactly these updates, so
  * their result is this result up to floating-point rounding order.
  *
- * Storage (Sect. 2.1): a field is [z][y][x] with x fastest.  Every array here
+ * Storage (Sect. 3.1): a field is [z][y][x] with x fastest.  Every array here
  * is a padded box of (nx+2h) x (ny+2h) x (nz+2h) doubles, contiguous; the
  * interior point (x,y,z), 0 <= x < nx etc., sits at padded (x+h, y+h, z+h).
  * The h-wide shell is the boundary: it is read by the stencil and never

@@ -213,7 +213,9 @@ int set_device(stencil_ctx* ctx) {
     return e == hipSuccess ? STENCIL_OK : dev_fail(e, "hipSetDevice");
 }
 
-// Naive time loop: nt launches, two-buffer storage.
+// Naive time loop: nt launches, two-buffer storage.  The boundary is time
+// independent: before the first step the level-0 buffer's shell is copied
+// into the other buffer, which the odd steps read.
 int run_naive(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
               int64_t nt) {
     const stn::dims d = to_dims(g);
@@ -221,6 +223,12 @@ int run_naive(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_c
     const bool bf16 = c->dtype == STENCIL_BF16;
     float* u0 = static_cast<float*>(g->u[0]);
     float* u1 = static_cast<float*>(g->u[1]);
+    if (nt >= 1) {
+        const bool lf = kind_leapfrog(kind);
+        hipError_t e = stn::launch_copy_shell(lf ? u0 : u1, lf ? u1 : u0, d, kind_radius(kind),
+                                              ctx->stream);
+        if (e != hipSuccess) return dev_fail(e, "shell copy");
+    }
     for (int64_t t = 0; t < nt; ++t) {
         hipError_t e;
         if (kind_leapfrog(kind)) {

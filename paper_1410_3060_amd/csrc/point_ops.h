@@ -1,4 +1,4 @@
-// Per-point stencil operators of Fig. 1b-1e (Sect. 2.1), one fixed FP32
+// Per-point stencil operators of Fig. 1b-1e (Sect. 3.1), one fixed FP32
 // evaluation order per kind.  Every kernel of the library (naive sweep,
 // temporally blocked wavefront, adjoint) evaluates a lattice update through
 // these functions, so all schemes round identically and the blocked result

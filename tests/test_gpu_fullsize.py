@@ -5,6 +5,11 @@ configuration bench.py times (default diamond width, default chunks).
 * the last step, sampled: the GPU's level nt at 3000 seeded interior points
   (faces, edges and corners included) against the oracle's single update of
   the GPU's own levels nt-1 (and nt-2), point by point;
+* the error of level nt after the full nt steps against the FP64 oracle over
+  the whole interior (rel-L2 <= 1e-5; the max-norm error is printed and
+  bounded), every workload, and with BF16 coefficients the parity against the
+  oracle on the BF16-rounded values plus the storage error against the oracle
+  on the FP32 values;
 * the adjoint of workload 5 (256^3, 200 steps, checkpoints every 14): the
   dot-product identity <F(d), s> = <d_{-1}, g_{-1}> + <d_0, g_0> for the linear
   map F: (u_{-1}, u_0) -> u_T, which holds at any size.
@@ -170,3 +175,47 @@ def test_fullsize_jacobi_adjoint_identities(index):
     print(f"{wl.name} adjoint: <F d, s> = {J:.9e}, <d, g_u0> = {rhs:.9e} (rel {e_dot:.2e}); "
           f"sum <W, g_W> / (nt J) - 1 = {e_hom:.2e}")
     assert e_dot <= 1e-5 and e_hom <= 1e-5
+
+
+def full_error(got, want, h):
+    g = got[h:-h, h:-h, h:-h].astype(np.float64)
+    w = want[h:-h, h:-h, h:-h]
+    d = g - w
+    return (float(np.linalg.norm(d.ravel()) / np.linalg.norm(w.ravel())),
+            float(np.abs(d).max() / np.abs(w).max()))
+
+
+def oracle_level_nt(wl, coef):
+    h = wl.halo
+    cf = None if coef is None else np.asarray(coef, dtype=np.float64)
+    if wl.kind in (4, 5):
+        return oracle.run(wl.kind, wl.u0.astype(np.float64), h, wl.nt,
+                          u_prev=wl.u_prev.astype(np.float64), coef=cf, w=oracle_weights(wl),
+                          alpha=wl.alpha)[1]
+    return oracle.run(wl.kind, wl.u0.astype(np.float64), h, wl.nt, coef=cf, w=oracle_weights(wl))
+
+
+@pytest.mark.parametrize("index,coef_dtype", [(1, "f32"), (2, "f32"), (3, "f32"), (4, "f32"),
+                                              (4, "bf16"), (5, "f32")])
+def test_fullsize_full_nt_error_vs_oracle(index, coef_dtype):
+    """Level nt after the whole run (blocked scheme, which equals the naive one
+    bit for bit) against the FP64 oracle on the very same stored inputs."""
+    import torch
+    wl = workloads.make(index, coef_dtype=coef_dtype)
+    h = wl.halo
+    top, _ = run_levels(wl, st.BLOCKED, wl.nt, coef_to_dev(wl))
+    got = host(top)
+    del top
+    torch.cuda.empty_cache()
+    want = oracle_level_nt(wl, wl.coef_values_f32() if wl.coef is not None else None)
+    e2, em = full_error(got, want, h)
+    print(f"{wl.name} {coef_dtype}: level {wl.nt} vs FP64 oracle: rel-L2 {e2:.3e}, "
+          f"max-norm {em:.3e}")
+    assert e2 <= 1e-5
+    assert em <= 1e-4
+    if coef_dtype == "bf16":
+        del want
+        ref = oracle_level_nt(wl, wl.coef)  # the unrounded FP32 values
+        s2, sm = full_error(got, ref, h)
+        print(f"{wl.name} BF16 storage error vs the FP32-coefficient oracle: rel-L2 {s2:.3e}, "
+              f"max-norm {sm:.3e} (target rel-L2 1e-3)")
