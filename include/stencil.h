@@ -152,6 +152,26 @@ int stencil_create(stencil_ctx** out, stencil_scheme scheme, const stencil_tunin
 int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
                 const stencil_coeffs* coeffs, int64_t nt, int* result_slot);
 
+/* Allocation-free variant of stencil_run for the blocked scheme, for callers
+   that cannot allocate device memory: code being captured into a HIP graph,
+   tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+   results (bit for bit) and result slot as stencil_run on a STENCIL_BLOCKED
+   context; the context's scheme must be STENCIL_BLOCKED
+   (STENCIL_ERR_UNSUPPORTED otherwise) and ckpt_every 0 (no recording).
+   It calls no hipMalloc, hipFree or other allocating routine: the blocked
+   scheme's second frontier pair lives in a static device array of the
+   library, 128 MiB per GPU, held from the library's load until the process
+   ends.  Grids whose two frontier fields (each spanning the padded field, at
+   the caller's row alignment) need more than 128 MiB are rejected with
+   STENCIL_ERR_UNSUPPORTED before any HIP call; that is about 16.7 M elements
+   per field, e.g. 250^3 with halo 4.  Every call on a GPU uses that GPU's
+   one array: calls that overlap in time on one GPU (other streams, other
+   contexts, other threads) race and give wrong results; calls in one stream
+   are ordered and safe.  The array keeps the previous call's contents; the
+   scheme writes every value it reads before reading it. */
+int stencil_run_noalloc(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
+                        const stencil_coeffs* coeffs, int64_t nt, int* result_slot);
+
 /* Reverse time stepping (adjoint) for kinds 2, 3 and 5.
 
    Kinds 2 and 3 (Fig. 1c, 1d).  With A = A(W) the sweep operator on the

@@ -67,8 +67,9 @@ class _Tuning(ctypes.Structure):
                 ("ckpt_every", ctypes.c_int32), ("workspace_limit", ctypes.c_int64)]
 
 
-EXPORTS = ("stencil_create", "stencil_run", "stencil_adjoint", "stencil_sync",
-           "stencil_destroy", "stencil_last_error", "stencil_plan_rows", "stencil_default_dw")
+EXPORTS = ("stencil_create", "stencil_run", "stencil_run_noalloc", "stencil_adjoint",
+           "stencil_sync", "stencil_destroy", "stencil_last_error", "stencil_plan_rows",
+           "stencil_default_dw")
 
 _lib = None
 
@@ -88,6 +89,8 @@ def load(path: Optional[str] = None):
     lib.stencil_run.argtypes = [vp, ctypes.c_int, ctypes.POINTER(_Grid), ctypes.POINTER(_Coeffs),
                                 i64, ctypes.POINTER(ctypes.c_int)]
     lib.stencil_run.restype = ctypes.c_int
+    lib.stencil_run_noalloc.argtypes = lib.stencil_run.argtypes
+    lib.stencil_run_noalloc.restype = ctypes.c_int
     lib.stencil_adjoint.argtypes = [vp, ctypes.c_int, ctypes.POINTER(_Grid),
                                     ctypes.POINTER(_Coeffs), i64, vp, vp, vp, vp]
     lib.stencil_adjoint.restype = ctypes.c_int
@@ -205,6 +208,18 @@ class Context:
         slot = ctypes.c_int(-1)
         _check(load().stencil_run(self._h, kind, ctypes.byref(g), ctypes.byref(c), int(nt),
                                   ctypes.byref(slot)))
+        return slot.value
+
+    def run_noalloc(self, kind: int, u0, u1, nt: int, *, halo: int, coef=None, w=(),
+                    alpha: float = 0.0) -> int:
+        """As run() on a BLOCKED context, allocating nothing (the library's
+        static scratch holds the second frontier pair); see
+        stencil_run_noalloc in include/stencil.h."""
+        g = grid_struct(u0, u1, halo)
+        c = coeff_struct(kind, u0, coef, w, alpha)
+        slot = ctypes.c_int(-1)
+        _check(load().stencil_run_noalloc(self._h, kind, ctypes.byref(g), ctypes.byref(c),
+                                          int(nt), ctypes.byref(slot)))
         return slot.value
 
     def adjoint(self, u_prev, u0, nt: int, *, halo: int, coef, w, seed, grad_u0, grad_um1, grad_c):

@@ -265,6 +265,13 @@ int ensure_frontier(stencil_ctx* ctx, size_t bytes) {
     return STENCIL_OK;
 }
 
+// The context's frontier workspace for a blocked run on grid g (none for
+// the naive scheme).
+int ensure_frontier_for(stencil_ctx* ctx, const stencil_grid* g) {
+    if (ctx->scheme != STENCIL_BLOCKED) return STENCIL_OK;
+    return ensure_frontier(ctx, layout_of(g).bytes(2));
+}
+
 // Planes per z-chunk of the blocked kernel whose address window (the chunk
 // plus 2R(L+1) + 1 planes, from a base of the workgroup's own) stays below
 // 2^31 bytes, so that 32-bit offsets reach it; < 1 if none does.
@@ -296,8 +303,10 @@ int check_blocked(const stencil_ctx* ctx, int kind, const stencil_grid* g) {
 // when the number of rows is odd the initial state is first copied to the
 // workspace so that the last row writes the caller's buffers, with level nt in
 // the slot the two-buffer convention prescribes.
+// `frontier` is the second frontier pair (FL.bytes(2) bytes): the context's
+// workspace, or the library's scratch for the allocation-free entry point.
 int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
-                int64_t nt) {
+                int64_t nt, void* frontier) {
     const int R = kind_radius(kind);
     const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
     const int H = dw / (2 * R);
@@ -306,10 +315,8 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
     const stn::diamond_plan plan = stn::make_plan(R, dw, g->ny, nt);
     const field_layout FL = layout_of(g);
     const size_t fbytes = FL.span * sizeof(float);
-    int rc = ensure_frontier(ctx, FL.bytes(2));
-    if (rc) return rc;
-    float* w0 = FL.at(ctx->frontier, 0);
-    float* w1 = FL.at(ctx->frontier, 1);
+    float* w0 = FL.at(frontier, 0);
+    float* w1 = FL.at(frontier, 1);
     float* u0 = static_cast<float*>(g->u[0]);
     float* u1 = static_cast<float*>(g->u[1]);
     const bool lf = kind_leapfrog(kind);
@@ -498,8 +505,11 @@ int run_recorded(stencil_ctx* ctx, int kind, const stencil_grid* g, const stenci
                                            static_cast<const float*>(g->u[0]), to_dims(g),
                                            kind_radius(kind), ctx->stream);
             if (e != hipSuccess) return dev_fail(e, "checkpoint copy");
-            const int rc = ctx->scheme == STENCIL_NAIVE ? run_naive(ctx, kind, &sub, c, steps)
-                                                        : run_blocked(ctx, kind, &sub, c, steps);
+            int rc = ensure_frontier_for(ctx, &sub);
+            if (rc == STENCIL_OK)
+                rc = ctx->scheme == STENCIL_NAIVE
+                         ? run_naive(ctx, kind, &sub, c, steps)
+                         : run_blocked(ctx, kind, &sub, c, steps, ctx->frontier);
             if (rc) return rc;
         }
     }
@@ -864,8 +874,53 @@ int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
     } else if (ctx->scheme == STENCIL_NAIVE) {
         rc = run_naive(ctx, k, grid, coeffs, nt);
     } else {
-        rc = run_blocked(ctx, k, grid, coeffs, nt);
+        rc = ensure_frontier_for(ctx, grid);
+        if (rc == STENCIL_OK) rc = run_blocked(ctx, k, grid, coeffs, nt, ctx->frontier);
     }
+    if (rc) return rc;
+    if (result_slot) *result_slot = slot;
+    return STENCIL_OK;
+}
+
+int stencil_run_noalloc(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
+                        const stencil_coeffs* coeffs, int64_t nt, int* result_slot) {
+    if (!ctx) return fail(STENCIL_ERR_INVALID, "ctx is NULL");
+    const int k = (int)kind;
+    if (k < 1 || k > 5) return fail(STENCIL_ERR_INVALID, "unknown stencil kind %d", k);
+    int rc = validate_grid(k, grid);
+    if (rc) return rc;
+    rc = validate_coeffs(k, grid, coeffs);
+    if (rc) return rc;
+    if (nt < 0) return fail(STENCIL_ERR_INVALID, "nt=%lld is negative", (long long)nt);
+    if (ctx->scheme != STENCIL_BLOCKED)
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "stencil_run_noalloc runs the blocked scheme (the naive one allocates "
+                    "nothing: use stencil_run)");
+    if (ctx->tuning.dw != 0 && ctx->tuning.dw % (2 * kind_radius(k)) != 0)
+        return fail(STENCIL_ERR_INVALID, "dw=%d is not a multiple of 2R=%d", ctx->tuning.dw,
+                    2 * kind_radius(k));
+    if (ctx->tuning.ckpt_every > 0)
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "stencil_run_noalloc does not record checkpoints (ckpt_every must be 0)");
+    const int slot = kind_leapfrog(k) ? (int)((nt + 1) % 2) : (int)(nt % 2);
+    if (nt == 0 || empty(grid)) {
+        if (result_slot) *result_slot = slot;
+        return STENCIL_OK;
+    }
+    rc = check_blocked(ctx, k, grid);
+    if (rc) return rc;
+    const size_t need = layout_of(grid).bytes(2);
+    if (need > stn::kScratchBytes)
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "stencil_run_noalloc: the grid needs %zu bytes of frontier storage; the "
+                    "library's scratch holds %zu (two fields of at most about %zu elements)",
+                    need, stn::kScratchBytes, (stn::kScratchBytes - 256) / 8);
+    rc = set_device(ctx);
+    if (rc) return rc;
+    void* scratch = nullptr;
+    hipError_t e = stn::blocked_scratch(&scratch);
+    if (e != hipSuccess) return dev_fail(e, "hipGetSymbolAddress(scratch)");
+    rc = run_blocked(ctx, k, grid, coeffs, nt, scratch);
     if (rc) return rc;
     if (result_slot) *result_slot = slot;
     return STENCIL_OK;

@@ -40,6 +40,15 @@ struct blocked_row_args {
     bool coef_aligned = false;
 };
 
+// Device memory of the allocation-free blocked run (stencil_run_noalloc): a
+// file-scope device array of kScratchBytes, one copy per GPU, held from the
+// library's load to the end of the process.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+// Device address of that array on the current device (looked up once per
+// device with hipGetSymbolAddress, then cached).  Host code must use this
+// address, never the array's name.
+hipError_t blocked_scratch(void** ptr);
+
 bool blocked_supported(int kind, int dw);
 int blocked_default_dw(int kind);
 int blocked_max_xo(int kind, int dw);

@@ -39,6 +39,7 @@
 // launch writes.  The boundary shell is time independent and both frontier
 // buffers carry it, so boundary values are read like frontier values.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "blocked.h"
@@ -592,6 +593,30 @@ int cfg_xch(int kind, int H) {
 }
 
 }  // namespace
+
+// Scratch of the allocation-free entry point.  The name is a host-side
+// stand-in in host code: only the address from hipGetSymbolAddress, taken
+// with the device current, may reach a kernel or a copy.
+static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
+
+hipError_t blocked_scratch(void** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 bool blocked_supported(int kind, int dw) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;

@@ -199,3 +199,38 @@ def test_sync_and_destroy_without_work():
     st.load().stencil_destroy(h)
     st.load().stencil_destroy(None)
     assert st.load().stencil_sync(None) == 1
+
+
+def run_noalloc(h, kind, g, c, nt=3):
+    slot = ctypes.c_int(-7)
+    rc = st.load().stencil_run_noalloc(h, kind, ctypes.byref(g) if g else None,
+                                       ctypes.byref(c) if c else None, nt, ctypes.byref(slot))
+    return rc, slot.value
+
+
+def test_noalloc_entry_point_validates_before_any_device_call():
+    lib = st.load()
+    # the naive scheme allocates nothing: the entry point is for BLOCKED contexts
+    rc, h = make_ctx()
+    g = grid(halo=4)
+    assert run_noalloc(h, 3, g, coeffs(3, g))[0] == 2 and "blocked" in msg()
+    lib.stencil_destroy(h)
+    # no checkpoint recording (it needs workspace)
+    rc, h = make_ctx(scheme=st.BLOCKED, ckpt=3)
+    assert run_noalloc(h, 3, g, coeffs(3, g))[0] == 2 and "ckpt_every" in msg()
+    lib.stencil_destroy(h)
+    rc, h = make_ctx(scheme=st.BLOCKED)
+    try:
+        assert run_noalloc(None, 3, g, coeffs(3, g))[0] == 1
+        assert run_noalloc(h, 3, g, coeffs(3, g), nt=-1)[0] == 1
+        assert run_noalloc(h, 3, grid(halo=3), coeffs(3, g))[0] == 1 and "halo" in msg()
+        # nt = 0 is a no-op reporting the slot, as for stencil_run
+        rc, slot = run_noalloc(h, 4, g, coeffs(4, g), nt=0)
+        assert rc == 0 and slot == 1
+        # grids beyond the 128 MiB scratch are refused with a clear message:
+        # two padded 260^3 fields need 2 * 70.3 MB
+        gb = grid(nx=252, ny=252, nz=252, halo=4)
+        rc, _ = run_noalloc(h, 3, gb, coeffs(3, gb))
+        assert rc == 2 and "scratch" in msg() and "bytes" in msg()
+    finally:
+        lib.stencil_destroy(h)
