@@ -78,7 +78,10 @@ typedef enum {
     STENCIL_25PT_VAR = 3,
     /* Fig. 1e with scalar alpha (coeffs.alpha), R = 4:
        u_{n+1} = 2 u_n - u_{n-1} + alpha * L8(u_n),
-       L8(u) = w[0]*u + sum_{r=1..4} w[r]*(x pair + y pair + z pair at r). */
+       L8(u) = w[0]*u + sum_{r=1..4} w[r]*(x pair + y pair + z pair at r),
+       evaluated in FP32 as (w[0] + 6 sum_r w[r])*u + sum_r w[r]*(pairs - 6u)
+       (the same operator; its row sum stays zero after the weights are
+       rounded to FP32). */
     STENCIL_25PT_WAVE = 4,
     /* Fig. 1e with alpha a domain-sized array (K = 1), e.g. c(x) of the wave
        equation. */

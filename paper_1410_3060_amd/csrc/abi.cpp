@@ -190,6 +190,7 @@ stn::host_weights to_weights(const stencil_coeffs* c) {
     stn::host_weights w;
     for (int i = 0; i < 5; ++i) w.w[i] = (float)c->w[i];
     w.alpha = (float)c->alpha;
+    w.lres = (float)(c->w[0] + 6.0 * (c->w[1] + c->w[2] + c->w[3] + c->w[4]));
     return w;
 }
 

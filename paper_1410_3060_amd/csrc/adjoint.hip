@@ -452,6 +452,7 @@ hipError_t launch_adjoint_step(bool bf16, bool mu, const float* lam1, float* lam
         wd.w[i] = w[i];
     }
     wt.alpha = 1.0f;
+    wt.lres = (float)(w[0] + 6.0 * (w[1] + w[2] + w[3] + w[4]));
     const auto* c16 = static_cast<const uint16_t*>(coef);
     const auto* c32 = static_cast<const float*>(coef);
     if (mu)

@@ -528,6 +528,7 @@ hipError_t launch_inst(const blocked_row_args& a, hipStream_t s) {
     weights wt;
     for (int i = 0; i < 5; ++i) wt.w[i] = a.wt.w[i];
     wt.alpha = a.wt.alpha;
+    wt.lres = a.wt.lres;
     using bytes_t = std::conditional_t<WIN, uint64_t, uint32_t>;
     hipLaunchKernelGGL(kern, dim3(ntiles), dim3(NWV * 64), 0, s, a.ftop_o, a.fsub_o, a.ftop_n,
                        a.fsub_n, static_cast<const CT*>(a.coef), a.sk, a.d.nx, a.d.ny, a.d.nz, a.d.h,

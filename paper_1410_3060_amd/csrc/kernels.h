@@ -17,6 +17,7 @@ struct dims {
 struct host_weights {
     float w[5];
     float alpha;
+    float lres;  // w0 + 6 (w1 + w2 + w3 + w4), formed in double (see op_lap8)
 };
 
 // One naive time step (Sect. 4.1).  Jacobi kinds: out <- A(cur).  Leapfrog

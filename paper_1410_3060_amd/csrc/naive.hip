@@ -211,6 +211,7 @@ hipError_t launch_kind(const float* cur, const float* prev, float* out, const vo
     weights wt;
     for (int i = 0; i < 5; ++i) wt.w[i] = hw.w[i];
     wt.alpha = hw.alpha;
+    wt.lres = hw.lres;
     hipLaunchKernelGGL((naive_step_kernel<KIND, CT, RPT, NW>), dim3((unsigned)ntiles), dim3(NW * 64),
                        0, s,
                        cur, prev, out, static_cast<const CT*>(coef), sk, d.nx, d.ny, d.nz, d.sy,

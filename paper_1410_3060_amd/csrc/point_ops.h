@@ -28,10 +28,14 @@ __device__ __forceinline__ float load_coef(const uint16_t* p, int64_t i) {
     return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
 }
 
-// Scalar weights passed by value to the kernels.
+// Scalar weights passed by value to the kernels.  lres is the centre
+// weight that L8 keeps after its neighbour terms are written as differences
+// from the centre: w0 + 6 (w1 + w2 + w3 + w4), rounded once from double on
+// the host (zero for the 8th-order weights).
 struct weights {
     float w[5];
     float alpha;
+    float lres;
 };
 
 // Neighbourhood of one point: centre value, the six axis pairs per radius
@@ -75,12 +79,20 @@ __device__ __forceinline__ float op_25pt_var(const float (&W)[13], const nbhd<4>
     return a;
 }
 
-// L8 of Fig. 1e: w0*u, then for r = 1..4 w_r * ((x pair + y pair) + z pair).
+// L8 of Fig. 1e, w0*u + sum_r w_r * (x pair + y pair + z pair), evaluated as
+//   lres*u + sum_{r=1..4} w_r * (((x pair + y pair) + z pair) - 6u),
+// lres = w0 + 6 sum_r w_r: the same operator, but each difference is exactly
+// zero on a constant field, so the FP32-rounded weights keep the operator's
+// zero row sum.  With w0 * u first the rounded weights leave a row sum of
+// about 1e-7 * |w0|, an extra alpha*eps*u term per leapfrog step whose effect
+// grows like nt^2: 3.4e-5 relative after 100 steps of the 512^3 constant-
+// coefficient workload, against 5e-7 in this form.
 __device__ __forceinline__ float op_lap8(const weights& wt, const nbhd<4>& n) {
-    float a = wt.w[0] * n.c;
+    const float six = 6.0f * n.c;
+    float a = wt.lres * n.c;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        a = __builtin_fmaf(wt.w[r + 1], (n.pair[0][r] + n.pair[1][r]) + n.pair[2][r], a);
+        a = __builtin_fmaf(wt.w[r + 1], ((n.pair[0][r] + n.pair[1][r]) + n.pair[2][r]) - six, a);
     return a;
 }
 

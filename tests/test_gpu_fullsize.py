@@ -219,3 +219,6 @@ def test_fullsize_full_nt_error_vs_oracle(index, coef_dtype):
         s2, sm = full_error(got, ref, h)
         print(f"{wl.name} BF16 storage error vs the FP32-coefficient oracle: rel-L2 {s2:.3e}, "
               f"max-norm {sm:.3e} (target rel-L2 1e-3)")
+        # the BF16 target, judged as stated: rel-L2 of the BF16-storage run
+        # against the oracle on the unrounded coefficients
+        assert s2 <= 1e-3
