@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libstencil.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("STENCIL_ARCH", "gfx950")
 
-SOURCES = ["naive.hip", "blocked.hip", "adjoint.hip", "adjoint_jacobi.hip", "abi.cpp"]
+SOURCES = ["naive.hip", "blocked.hip", "mwd.hip", "adjoint.hip", "adjoint_jacobi.hip", "abi.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
         shutil.copytree(os.path.join(os.path.dirname(HERE), "include"), os.path.join(snap, "include"))
         src_dir = os.path.join(snap, "paper_1410_3060_amd", "csrc")
         srcs = [s for s in SOURCES if os.path.exists(os.path.join(src_dir, s))]
-        with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+        with ThreadPoolExecutor(max_workers=min(6, len(srcs))) as ex:
             objs = list(ex.map(lambda s: _compile(s, src_dir, build_dir), srcs))
     finally:
         shutil.rmtree(snap, ignore_errors=True)

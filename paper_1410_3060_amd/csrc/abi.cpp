@@ -60,6 +60,12 @@ struct stencil_ctx {
     // blocked scheme frontier buffers (two pairs of fields)
     void* frontier = nullptr;
     size_t frontier_bytes = 0;
+    // radius-4 blocked scheme: halo exchange buffer of the workgroup teams
+    // (the error flag follows it), and the flag the last run used
+    void* xchg = nullptr;
+    size_t xchg_bytes = 0;
+    int* err_dev = nullptr;
+    uint32_t tag = 0;  // launch tag of the last row launch (1 .. 4095)
     // checkpoints recorded by stencil_run for stencil_adjoint (kinds 2, 3, 5)
     struct recording {
         bool valid = false;
@@ -266,6 +272,22 @@ int ensure_frontier(stencil_ctx* ctx, size_t bytes) {
     return STENCIL_OK;
 }
 
+// Device workspace for the exchange buffer of the radius-4 blocked scheme.
+int ensure_exchange(stencil_ctx* ctx, size_t bytes) {
+    if (ctx->xchg && ctx->xchg_bytes >= bytes) return STENCIL_OK;
+    if (ctx->xchg) {
+        ws_free(ctx, ctx->xchg);
+        ctx->xchg = nullptr;
+        ctx->xchg_bytes = 0;
+    }
+    void* p = nullptr;
+    int rc = ws_alloc(ctx, bytes, &p);
+    if (rc) return rc;
+    ctx->xchg = p;
+    ctx->xchg_bytes = bytes;
+    return STENCIL_OK;
+}
+
 // The context's frontier workspace for a blocked run on grid g (none for
 // the naive scheme).
 int ensure_frontier_for(stencil_ctx* ctx, const stencil_grid* g) {
@@ -306,8 +328,10 @@ int check_blocked(const stencil_ctx* ctx, int kind, const stencil_grid* g) {
 // the slot the two-buffer convention prescribes.
 // `frontier` is the second frontier pair (FL.bytes(2) bytes): the context's
 // workspace, or the library's scratch for the allocation-free entry point.
+// The radius-4 kinds also need the teams' exchange buffer: `xchg` (xcap
+// bytes) or, if NULL, the context's workspace.
 int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
-                int64_t nt, void* frontier) {
+                int64_t nt, void* frontier, void* xchg = nullptr, size_t xcap = 0) {
     const int R = kind_radius(kind);
     const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
     const int H = dw / (2 * R);
@@ -347,11 +371,74 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         if (e == hipSuccess) e = stn::launch_copy_shell(w1, shell, d, R, ctx->stream);
         if (e != hipSuccess) return dev_fail(e, "shell copy");
     }
+    const bool bf16 = c->dtype == STENCIL_BF16;
+    if (stn::mwd_supported(kind, dw)) {
+        size_t xbytes = 0;
+        e = stn::mwd_workspace(kind, bf16, dw, g->nx, &xbytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(STENCIL_ERR_UNSUPPORTED,
+                        "blocked scheme: no team of workgroups for nx=%d fits the device (%s)",
+                        g->nx, hipGetErrorString(e));
+        }
+        const size_t need = xbytes + 256;  // the error flag follows the buffer
+        if (!xchg) {
+            int rc = ensure_exchange(ctx, need);
+            if (rc) return rc;
+            xchg = ctx->xchg;
+        } else if (need > xcap) {
+            return fail(STENCIL_ERR_UNSUPPORTED,
+                        "stencil_run_noalloc: the frontier pair and the %zu-byte halo exchange "
+                        "buffer exceed the library's %zu-byte scratch",
+                        need, stn::kScratchBytes);
+        }
+        int* err = reinterpret_cast<int*>(static_cast<char*>(xchg) + xbytes);
+        ctx->err_dev = err;
+        e = stn::launch_fill_u32(xchg, need / 4, 0u, ctx->stream);
+        if (e != hipSuccess) return dev_fail(e, "exchange clear");
+        for (const stn::diamond_row& row : plan.rows) {
+            stn::mwd_row_args a;
+            a.ftop_o = rt;
+            a.fsub_o = rs;
+            a.ftop_n = reading_caller ? w0 : fin_top;
+            a.fsub_n = reading_caller ? w1 : fin_sub;
+            a.coef = c->arrays;
+            a.sk = c->sk;
+            a.d = d;
+            a.wt = to_weights(c);
+            a.t0 = row.t0;
+            a.nt = nt;
+            a.first_centre = row.first_centre;
+            a.n_diamonds = row.n_diamonds;
+            a.dw = dw;
+            a.zchunk = ctx->tuning.zchunk;
+            a.field_bytes = fbytes;
+            a.coef_bytes = FL.span * (bf16 ? 2 : 4);
+            a.xbuf = xchg;
+            a.xbuf_bytes = xbytes;
+            a.coef_aligned = bf16 && (reinterpret_cast<uintptr_t>(c->arrays) & 3u) == 0 &&
+                             c->sk % 2 == 0 && g->sz % 2 == 0;
+            a.err = err;
+            // stamps differ between consecutive launches; after 4095 launches
+            // the tags repeat and the buffer is cleared again
+            if (ctx->tag >= 4095) {
+                ctx->tag = 0;
+                e = stn::launch_fill_u32(xchg, xbytes / 4, 0u, ctx->stream);
+                if (e != hipSuccess) return dev_fail(e, "exchange clear");
+            }
+            a.tag = ++ctx->tag;
+            e = stn::launch_mwd_row(kind, bf16, a, ctx->stream);
+            if (e != hipSuccess) return dev_fail(e, "blocked row launch");
+            rt = a.ftop_n;
+            rs = a.fsub_n;
+            reading_caller = !reading_caller;
+        }
+        return STENCIL_OK;
+    }
     const int64_t zmax = blocked_max_zchunk(kind, dw, g);
     const int xomax = stn::blocked_max_xo(kind, dw);
     const int gx = (g->nx + xomax - 1) / xomax;
     const int xo = (g->nx + gx - 1) / gx;
-    const bool bf16 = c->dtype == STENCIL_BF16;
     const bool coef_aligned = bf16 && (reinterpret_cast<uintptr_t>(c->arrays) & 3u) == 0 &&
                               c->sk % 2 == 0 && g->sz % 2 == 0;
     // workgroups of the row kernel the device holds at once, for the z-chunk
@@ -921,7 +1008,9 @@ int stencil_run_noalloc(stencil_ctx* ctx, stencil_kind kind, const stencil_grid*
     void* scratch = nullptr;
     hipError_t e = stn::blocked_scratch(&scratch);
     if (e != hipSuccess) return dev_fail(e, "hipGetSymbolAddress(scratch)");
-    rc = run_blocked(ctx, k, grid, coeffs, nt, scratch);
+    const size_t fpair = (need + 255) / 256 * 256;
+    rc = run_blocked(ctx, k, grid, coeffs, nt, scratch, static_cast<char*>(scratch) + fpair,
+                     stn::kScratchBytes - fpair);
     if (rc) return rc;
     if (result_slot) *result_slot = slot;
     return STENCIL_OK;
@@ -964,6 +1053,19 @@ int stencil_sync(stencil_ctx* ctx) {
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return dev_fail(e, "hipStreamSynchronize");
+    if (ctx->err_dev) {
+        // a halo of the radius-4 blocked scheme that never arrived
+        int flag = 0;
+        e = hipMemcpy(&flag, ctx->err_dev, sizeof flag, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return dev_fail(e, "error flag read");
+        if (flag) {
+            const int zero = 0;
+            (void)hipMemcpy(ctx->err_dev, &zero, sizeof zero, hipMemcpyHostToDevice);
+            return fail(STENCIL_ERR_DEVICE,
+                        "blocked scheme: a workgroup waited in vain for a neighbour's halo; the "
+                        "results of the run are invalid");
+        }
+    }
     return STENCIL_OK;
 }
 

@@ -49,6 +49,38 @@ constexpr size_t kScratchBytes = size_t(128) << 20;
 // address, never the array's name.
 hipError_t blocked_scratch(void** ptr);
 
+// Multi-workgroup diamonds for the radius-4 kinds (mwd.hip): one launch per
+// diamond row; teams of workgroups share a diamond, one 16-column x-slice
+// each, exchanging x-halos through `xbuf` (cleared to zero before the first
+// row of a run; `tag` 1 .. 4095 differs between consecutive launches).  A
+// halo that never arrives sets *err to non-zero.
+struct mwd_row_args {
+    const float* ftop_o;
+    const float* fsub_o;
+    float* ftop_n;
+    float* fsub_n;
+    const void* coef;
+    int64_t sk;
+    dims d;
+    host_weights wt;
+    int64_t t0, nt;
+    int first_centre, n_diamonds;
+    int dw;
+    int zchunk = 0;  // planes per z-chunk, 0 = chosen from the team count
+    uint64_t field_bytes, coef_bytes;
+    // BF16 arrays on 4-byte boundaries with even sk and sz: word loads
+    bool coef_aligned = false;
+    void* xbuf;
+    size_t xbuf_bytes;
+    int* err;
+    uint32_t tag;
+};
+bool mwd_supported(int kind, int dw);
+// bytes of exchange buffer the launches of (kind, dw) need on this device for nx
+hipError_t mwd_workspace(int kind, bool bf16, int dw, int nx, size_t* xbytes);
+hipError_t launch_mwd_row(int kind, bool bf16, const mwd_row_args& a, hipStream_t s);
+hipError_t launch_fill_u32(void* p, size_t words, uint32_t v, hipStream_t s);
+
 bool blocked_supported(int kind, int dw);
 int blocked_default_dw(int kind);
 int blocked_max_xo(int kind, int dw);

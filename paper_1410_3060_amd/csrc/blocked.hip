@@ -571,18 +571,6 @@ hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
         if (H == 4) return launch_cfg<KIND, CT, 4, 10, 1, true>(a, s);
         if (H == 5) return launch_cfg<KIND, CT, 5, 12, 1, true, false, 1>(a, s);
         if (H == 6) return launch_cfg<KIND, CT, 6, 14, 1, true, false, 1>(a, s);
-    } else if constexpr (KIND == 5) {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, true, 1>(a, s);
-    } else if constexpr (KIND == 4) {
-        if (H == 2) return launch_cfg<KIND, CT, 2, 16, 1, false, true, 1>(a, s);
-    } else {
-        // FP32: level 0 from the frontier (fewer registers); BF16: from the
-        // shell ring (without it the compiler serialises the word loads)
-        if constexpr (std::is_same<CT, float>::value) {
-            if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, false, 2>(a, s);
-        } else {
-            if (H == 2) return launch_cfg<KIND, CT, 2, 12, 1, false, true, 2>(a, s);
-        }
     }
     return hipErrorInvalidValue;
 }
@@ -620,16 +608,16 @@ hipError_t blocked_scratch(void** ptr) {
 }
 
 bool blocked_supported(int kind, int dw) {
-    const int R = (kind == 1 || kind == 2) ? 1 : 4;
-    if (dw % (2 * R) != 0) return false;
-    const int H = dw / (2 * R);
-    return R == 1 ? (H >= 2 && H <= 6) : (H == 2);
+    if (kind >= 3) return mwd_supported(kind, dw);
+    if (dw % 2 != 0) return false;
+    const int H = dw / 2;
+    return H >= 2 && H <= 6;
 }
 
 // measured on MI355X over cubes of 64 .. 512: 6 for both 7-point stencils
-// (best or within 10 % of the best at every size), the only width provided
-// for radius 4
-int blocked_default_dw(int kind) { return (kind == 1 || kind == 2) ? 6 : 16; }
+// (best or within 10 % of the best at every size); 24 for the radius-4
+// stencils (multi-workgroup diamonds)
+int blocked_default_dw(int kind) { return (kind == 1 || kind == 2) ? 6 : 24; }
 
 int blocked_max_xo(int kind, int dw) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;
@@ -642,9 +630,6 @@ hipError_t launch_blocked_row(int kind, bool bf16, const blocked_row_args& a, hi
     switch (kind) {
     case 1: return launch_kind<1, float>(a, s);
     case 2: return bf16 ? launch_kind<2, uint16_t>(a, s) : launch_kind<2, float>(a, s);
-    case 3: return bf16 ? launch_kind<3, uint16_t>(a, s) : launch_kind<3, float>(a, s);
-    case 4: return launch_kind<4, float>(a, s);
-    case 5: return bf16 ? launch_kind<5, uint16_t>(a, s) : launch_kind<5, float>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -21,7 +21,8 @@ from . import (BLOCKED, KIND_25PT_WAVE, KIND_7PT_CONST, L8_WEIGHTS, LEAPFROG, NA
                RADIUS, Context, alloc_field, default_dw, field_like)
 
 # diamond widths the blocked kernel is compiled for, per stencil radius
-PROVIDED_DW = {1: (4, 6, 8, 10, 12), 4: (16,)}
+PROVIDED_DW = {1: (4, 6, 8, 10, 12), 2: (4, 6, 8, 10, 12), 3: (16, 24), 4: (16, 24, 32),
+               5: (16, 24, 32)}
 
 
 def _inputs(kind, n3, h, coef_dtype, seed):
@@ -92,7 +93,7 @@ def autotune(kind: int, n3, nt: int, *, halo: Optional[int] = None, coef_dtype: 
     nx, ny, nz = n3
     lups = nx * ny * nz * nt
     inputs = _inputs(kind, n3, h, coef_dtype, seed)
-    cands = [(NAIVE, 0)] + [(BLOCKED, d) for d in (dws or PROVIDED_DW[RADIUS[kind]])]
+    cands = [(NAIVE, 0)] + [(BLOCKED, d) for d in (dws or PROVIDED_DW[kind])]
     results = []
     for scheme, d in cands:
         t = time_run(kind, scheme, n3, nt, dw=d, halo=h, reps=reps, inputs=inputs)

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 SIZES = {1: (150, 45, 23), 2: (70, 37, 19), 3: (130, 41, 29), 4: (131, 39, 26), 5: (97, 35, 27)}
 # diamond widths per workload: R = 1 for workloads 1 and 3, R = 4 for 2, 4 and 5
-DWS = {1: [8, 4, 12], 2: [16], 3: [8, 4, 12], 4: [16], 5: [16]}
+DWS = {1: [8, 4, 12], 2: [24, 16, 32], 3: [8, 4, 12], 4: [24, 16], 5: [24, 16, 32]}
 
 
 def both(wl, dw, nt, **kw):
@@ -121,6 +121,23 @@ def test_blocked_thin_and_tiny():
         nb, _ = run_gpu(wl, st.NAIVE)
         bl, _ = run_gpu(wl, st.BLOCKED, dw=8)
         assert_bitwise(bl, nb, f"7pt var n={n}")
+
+
+@pytest.mark.parametrize("index", [2, 4, 5])
+def test_blocked_radius4_other_widths_and_shapes(index):
+    """The multi-workgroup diamonds of the radius-4 stencils at every provided
+    width, on one slice (nx <= 16), many slices with a ragged last one, thin
+    grids and nt around the diamond half-heights."""
+    shapes = [(16, 30, 21), (9, 11, 40), (53, 7, 3), (1, 1, 1), (40, 66, 9)]
+    for dw in DWS[index]:
+        for n3 in shapes:
+            for nt in (2, 7):
+                print(f"workload {index} dw {dw} n {n3} nt {nt}", flush=True)
+                wl = workloads.make(index, n=n3, nt=nt)
+                nb, nb_prev, bl, bl_prev = both(wl, dw, nt)
+                assert_bitwise(bl, nb, f"workload {index} dw {dw} n {n3} nt {nt}")
+                if nb_prev is not None:
+                    assert_bitwise(bl_prev, nb_prev, f"workload {index} dw {dw} n {n3} nt {nt} prev")
 
 
 @pytest.mark.parametrize("index", [3, 4, 5])

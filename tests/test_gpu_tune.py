@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("kind,n3", [(2, (70, 40, 30)), (3, (66, 36, 20))])
 def test_autotune_candidates_and_best(kind, n3):
     r = tune.autotune(kind, n3, 8, reps=1)
-    widths = tune.PROVIDED_DW[st.RADIUS[kind]]
+    widths = tune.PROVIDED_DW[kind]
     assert len(r["results"]) == 1 + len(widths)
     assert [x["dw"] for x in r["results"][1:]] == list(widths)
     assert all(x["glups"] > 0 for x in r["results"])
