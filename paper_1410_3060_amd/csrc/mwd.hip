@@ -101,38 +101,483 @@ constexpr int exoff(int B) {
     return o;
 }
 
-template <int KIND, typename CT, int H, int NXW, bool LRING, bool ALN, int CG>
-__global__ __launch_bounds__(2 * H * NXW * 64) void mwd_row_kernel(mwd_kargs a) {
-    constexpr int R = kR;
-    constexpr int K = kind_traits<KIND>::K;
-    constexpr int KS = kslots<KIND>;
-    constexpr bool LF = kind_traits<KIND>::leapfrog;
-    constexpr int L = 2 * H - 1;
-    constexpr int Q = 2 * R + 1;
-    constexpr int DW = 2 * R * H;
-    constexpr int XS = 16 * NXW;
-    constexpr int XT = XS + 2 * R;
-    constexpr int YT = DW + 2 * R;
-    constexpr int NR0 = (L - 1) * R + 1;  // coefficient planes of band 0
-    constexpr int NEXT = exoff<H>(H);     // exchanged (band, level) pairs per side
-    constexpr uint32_t RECB = 2u * 2u * NEXT * 16u * 8u;  // bytes per workgroup and slot
-    constexpr uint32_t CB = sizeof(CT);
-    constexpr int KG = K > 0 ? K : 1;
+// Compile-time configuration of one kernel instance.
+template <int KIND_, typename CT_, int H_, int NXW_, bool LRING_, bool ALN_, int CG_>
+struct mwd_cfg {
+    static constexpr int KIND = KIND_, H = H_, NXW = NXW_, CG = CG_;
+    using CT = CT_;
+    static constexpr bool LRING = LRING_, ALN = ALN_;
+    static constexpr int R = kR;
+    static constexpr int K = kind_traits<KIND>::K;
+    static constexpr int KS = kslots<KIND>;
+    static constexpr int KG = K > 0 ? K : 1;
+    static constexpr int NG = (KG + CG - 1) / CG;  // coefficient buffer resources
+    static constexpr bool LF = kind_traits<KIND>::leapfrog;
+    static constexpr int L = 2 * H - 1;
+    static constexpr int Q = 2 * R + 1;
+    static constexpr int DW = 2 * R * H;
+    static constexpr int XS = 16 * NXW;
+    static constexpr int XT = XS + 2 * R;
+    static constexpr int YT = DW + 2 * R;
+    static constexpr int NR0 = (L - 1) * R + 1;  // coefficient planes of band 0
+    static constexpr int NEXT = exoff<H>(H);     // exchanged (band, level) pairs per side
+    static constexpr uint32_t RECB = 2u * 2u * NEXT * 16u * 8u;  // bytes per workgroup and slot
+    static constexpr uint32_t CB = sizeof(CT);
+    static constexpr int NW = 4 * NXW;  // waves: two band groups x two sides x NXW
+    using RT = std::conditional_t<std::is_same<CT, float>::value, float, uint16_t>;
     static_assert(!LRING || K > 1, "the LDS ring is for the 13-array stencil");
     static_assert(!ALN || CB == 2, "word loads are for BF16 arrays");
+};
 
-    __shared__ float tile[2][L][YT][XT];
-    __shared__ float spare[2 * H * NXW][64];  // target of lanes with nothing to stage
-    using RT = std::conditional_t<std::is_same<CT, float>::value, float, uint16_t>;
-    __shared__ RT ring0[LRING ? NR0 : 1][LRING ? K : 1][LRING ? 2 * NXW : 1][64];
+// Bands per wave group, chosen so that both groups compute about the same
+// number of levels per step (band B computes 2H-1-2B levels):
+// H = 2: {0}, {1};  H = 3: {0}, {1, 2};  H = 4: {0, 3}, {1, 2}.
+template <int H>
+constexpr int gband(int g, int i) {
+    if (H == 2) return i == 0 ? g : -1;
+    if (H == 3) return g == 0 ? (i == 0 ? 0 : -1) : (i == 0 ? 1 : 2);
+    return g == 0 ? (i == 0 ? 0 : 3) : (i == 0 ? 1 : 2);
+}
 
-    const int lane = threadIdx.x & 63;
+// What one wave knows about the item and the lanes it runs (shared by the
+// bands of the wave).
+template <class C>
+struct mwd_item {
+    const mwd_kargs* a;
+    float (*tile)[C::L][C::YT][C::XT];
+    typename C::RT (*ring0)[C::LRING ? C::K : 1][C::LRING ? 2 * C::NXW : 1][64];
+    float* spare;  // this lane's slot for lanes with nothing to stage
+    rsrc_t rFT, rFS, rNT, rNS, rX;
+    rsrc_t rC[C::NG];
+    uint32_t skb, sz4, szc;
+    int yc, z0, z1, zw, s_begin, s_end, t0, nt;
+    // lanes
+    int lane, side, xw, ringw, cx, rr, x, xl;
+    int hside, hr, hc, xh, eedge, ecol;
+    bool hlane, hx_nb;
+    uint32_t my_rec, nb_rec;
+
+    __device__ __forceinline__ uint32_t stamp(uint32_t q) const { return (a->tag << 20) | (q & 0xfffffu); }
+    __device__ __forceinline__ int clampt(int t) const { return t < 0 ? 0 : (t > nt ? nt : t); }
+    __device__ __forceinline__ uint32_t plane_off(int z, uint32_t stride) const {
+        return (uint32_t)(z - zw) * stride;
+    }
+    __device__ __forceinline__ rsrc_t crs(int kk) const { return rC[kk / C::CG]; }
+    __device__ __forceinline__ uint32_t csoff(int kk) const { return (uint32_t)(kk % C::CG) * skb; }
+};
+
+// One band-side of a diamond, run by one wave: old top level JO (B, or H in
+// the first row of a run), new top level JN (2H-1-B; 0 = computed at run
+// time for the first and last rows).
+template <class C, int B, int JO, int JN>
+struct mwd_band {
+    static constexpr int R = C::R, K = C::K, Q = C::Q, L = C::L, H = C::H;
+    static constexpr int XS = C::XS, XT = C::XT, YT = C::YT, NR0 = C::NR0;
+    static constexpr int J0 = B + 1, J1 = 2 * H - 1 - B;
+    static constexpr int NL = J1 - J0 + 1;
+    static constexpr bool RL = C::LRING && B == 0;  // coefficient ring in LDS
+    static constexpr int NR = RL ? 1 : (K > 0 ? (NL - 1) * R + 1 : 1);
+    static constexpr int KR = (K > 0 && !RL) ? K : 1;
+    static constexpr int NSH = (J1 - B) * R + 1;
+    static constexpr int NX = nex<H>(B) > 0 ? nex<H>(B) : 1;
+    static constexpr int QS = R + 2;
+    static constexpr int jo = JO;
+
+    int jn;
+    int ylt, xt, hty, htc, ylf;
+    bool intr, flank_on;
+    uint32_t o_ot, o_ht, o_fl, o_c, csel;
+    int rslot;
+    float q[NL][Q];    // q[i][.]: level B+i at planes z_{B+i+1} - R .. + R
+    float qt[R];       // level J1, last R steps (qt[0] newest)
+    float qs[QS];      // old sub, last R+2 steps (qs[0] newest)
+    float sh[NSH];     // old-top loads, last NSH steps (sh[0] newest)
+    float cr[NR][KR];  // coefficient ring: cr[i] = plane s - B R - i
+    float p_ot[2], p_qs[2], p_ht[2], p_fl[2];
+    float p_c[2][C::KG];
+    uint32_t x_v[NX], x_s[NX];
+
+    __device__ __forceinline__ uint32_t xoff(const mwd_item<C>& I, int e, int l) const {
+        return (uint32_t)(((e * 2 + I.side) * C::NEXT + exoff<H>(B) + (l - J0)) * 128);
+    }
+
+    __device__ __forceinline__ void init(const mwd_item<C>& I) {
+        const mwd_kargs& a = *I.a;
+        // new top: 2H-1-B clipped to nt; a band already at nt copies its pair
+        if (JN > 0) {
+            jn = JN;
+        } else {
+            jn = I.t0 + B > I.nt ? JO : max(JO, I.clampt(I.t0 + J1) - I.t0);
+        }
+        const int ybase = I.side ? I.yc + B * R : I.yc - (B + 1) * R;
+        const int y = ybase + I.rr;
+        ylt = I.side ? (H + 1) * R + B * R + I.rr : (H - B) * R + I.rr;  // tile row
+        xt = R + I.xl;                                                     // tile column
+        const bool need = I.x >= -R && I.x < a.nx + R && y >= -R && y < a.ny + R;
+        intr = I.x >= 0 && I.x < a.nx && y >= 0 && y < a.ny;
+        const uint32_t rc = (uint32_t)((int64_t)(y + a.hh) * a.sy + (I.x + a.hh));  // element
+        const int yh = ybase + I.hr;
+        const bool hneed = I.hlane && I.xh >= -R && I.xh < a.nx + R && yh >= -R && yh < a.ny + R;
+        const uint32_t rch = (uint32_t)((int64_t)(yh + a.hh) * a.sy + (I.xh + a.hh));
+        htc = I.hside ? R + XS + I.hc : I.hc;  // tile column of the halo lane
+        hty = I.side ? (H + 1) * R + B * R + I.hr : (H - B) * R + I.hr;
+        // flank rows (band H-1): the neighbour diamonds' rows next to this one
+        const int yf = I.side ? I.yc + H * R + I.rr : I.yc - (H + 1) * R + I.rr;
+        ylf = I.side ? (2 * H + 1) * R + I.rr : I.rr;
+        const bool fneed = B == H - 1 && I.x >= -R && I.x < a.nx + R && yf >= -R && yf < a.ny + R;
+        const uint32_t rcf = (uint32_t)((int64_t)(yf + a.hh) * a.sy + (I.x + a.hh));
+        const int jf = I.clampt(I.t0 + H - 1) - I.t0;
+        flank_on = B == H - 1 && JO == H - 1 && jn >= H && jf == H - 1;
+        // Per-lane running offsets of the prefetched streams, for the step
+        // the next prefetch is for.  Every offset advances by one plane per
+        // step; a lane that needs nothing starts at kNone and stays at or
+        // above 2^31 (an item's window spans less than 2^31 bytes).
+        const int sp = I.s_begin;  // first prefetched step
+        o_ot = need ? rc * 4u + I.plane_off(sp - (JO - 1) * R, I.sz4) : kNone;
+        o_ht = (hneed && jn > JO) ? rch * 4u + I.plane_off(sp + 1 - JO * R, I.sz4) : kNone;
+        o_fl = (fneed && flank_on) ? rcf * 4u + I.plane_off(sp + 1 - (H - 1) * R, I.sz4) : kNone;
+        // coefficients of interior points only
+        const int cz0 = RL ? sp : sp - B * R;
+        o_c = (need && intr) ? rc * C::CB + I.plane_off(cz0, I.szc) : kNone;
+        // BF16 word loads: the element's half of its 32-bit word is fixed
+        // per lane (even strides, word-aligned arrays)
+        csel = (o_c & 2u) ? 0x03020c0cu : 0x01000c0cu;
+        rslot = ((I.s_begin % NR0) + NR0) % NR0;
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+#pragma unroll
+            for (int m = 0; m < Q; ++m) q[i][m] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < R; ++m) qt[m] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < QS; ++m) qs[m] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < NSH; ++m) sh[m] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) cr[i][kk] = 0.0f;
+    }
+
+    template <int SL>
+    __device__ __forceinline__ void prefetch(const mwd_item<C>& I) {
+        p_ot[SL] = bload(I.rFT, o_ot, 0u);
+        // the old sub one plane above the old top's
+        p_qs[SL] = (C::LF || JO >= 1) ? bload(I.rFS, o_ot + I.sz4, 0u) : 0.0f;
+        p_ht[SL] = bload(I.rFT, o_ht, 0u);
+        p_fl[SL] = (B == H - 1) ? bload(I.rFT, o_fl, 0u) : 0.0f;
+        o_ot += I.sz4;
+        o_ht += I.sz4;
+        o_fl += I.sz4;
+        if constexpr (K > 0) {
+            if constexpr (C::ALN) {
+                uint32_t wv[K];
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk)
+                    wv[kk] = __builtin_amdgcn_raw_buffer_load_b32(I.crs(kk), o_c & ~3u, I.csoff(kk), 0);
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk)
+                    p_c[SL][kk] = __uint_as_float(__builtin_amdgcn_perm(wv[kk], wv[kk], csel));
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk)
+                    p_c[SL][kk] = cload(static_cast<const typename C::CT*>(nullptr), I.crs(kk), o_c, I.csoff(kk));
+            }
+            o_c += I.szc;
+        }
+    }
+
+    // halos of the computed levels jo+1 .. jn-1 that the staging at the end
+    // of step s writes: produced by the neighbours at step s+1-R, loaded at
+    // the start of step s (two steps of slack)
+    __device__ __forceinline__ void xload(const mwd_item<C>& I, uint32_t seq) {
+        const uint32_t slotb = ((seq + 1 - R) & (kSlots - 1)) * C::RECB;
+        const uint32_t want = I.stamp(seq + 1 - R);
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+            const int l = J0 + e;
+            x_v[e] = 0u;
+            x_s[e] = want;
+            if (nex<H>(B) > 0 && l > jo && l < jn) {
+                // from the neighbour slice, or the shell beyond the lattice
+                // (plane s + 1 - l R; o_ht is two steps ahead) for an edge slice
+                const uint32_t rec = I.nb_rec + slotb + xoff(I, I.hside ? 0 : 1, l) + (uint32_t)(I.hr * 4 + I.hc) * 8u;
+                const auto v = __builtin_amdgcn_raw_buffer_load_b64(I.rX, (I.hlane && I.hx_nb) ? rec : kNone, 0, kSC1);
+                const uint32_t sv = __builtin_amdgcn_raw_buffer_load_b32(
+                    I.rFT, (I.hlane && !I.hx_nb) ? o_ht - (uint32_t)(2 + (l - jo) * R) * I.sz4 : kNone, 0u, 0);
+                x_v[e] = I.hx_nb ? v[0] : sv;
+                x_s[e] = I.hx_nb ? v[1] : want;
+            }
+        }
+    }
+
+    // the levels of step s, the new frontier, the slice's edge columns
+    template <int P>
+    __device__ __forceinline__ void compute(const mwd_item<C>& I, int s, uint32_t seq) {
+        const mwd_kargs& a = *I.a;
+        const float ot = p_ot[P];
+#pragma unroll
+        for (int m = NSH - 1; m > 0; --m) sh[m] = sh[m - 1];
+        sh[0] = ot;
+#pragma unroll
+        for (int m = QS - 1; m > 0; --m) qs[m] = qs[m - 1];
+        qs[0] = p_qs[P];
+        if constexpr (K > 0) {
+            if constexpr (RL) {
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    if constexpr (std::is_same<typename C::RT, float>::value)
+                        I.ring0[rslot][kk][I.ringw][I.lane] = p_c[P][kk];
+                    else
+                        I.ring0[rslot][kk][I.ringw][I.lane] = (uint16_t)(__float_as_uint(p_c[P][kk]) >> 16);
+                }
+            } else {
+#pragma unroll
+                for (int i = NR - 1; i > 0; --i)
+#pragma unroll
+                    for (int kk = 0; kk < K; ++kk) cr[i][kk] = cr[i - 1][kk];
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) cr[0][kk] = p_c[P][kk];
+            }
+        }
+        // the old top enters the queue of level jo (or the top queue)
+        if constexpr (JO < J1) {
+#pragma unroll
+            for (int m = 0; m < Q - 1; ++m) q[JO - B][m] = q[JO - B][m + 1];
+            q[JO - B][Q - 1] = ot;
+        }
+        if constexpr (JO == J1) {
+#pragma unroll
+            for (int m = R - 1; m > 0; --m) qt[m] = qt[m - 1];
+            qt[0] = ot;
+        }
+        const float(*Pt)[YT][XT] = I.tile[P];
+        float vtop = ot, vsub = (jn == jo) ? qs[0] : ot;
+#pragma unroll
+        for (int jj = 0; jj < NL; ++jj) {
+            const int j = J0 + jj;
+            if (j > JO && j <= jn) {
+                const int z = s - (j - 1) * R;
+                float v;
+                {
+                    float Wv[C::KS];
+                    Wv[0] = 0.0f;
+                    if constexpr (K > 0) {
+                        if constexpr (RL) {
+                            int slot = rslot - (j - 1) * R;
+                            slot = slot < 0 ? slot + NR0 : slot;
+#pragma unroll
+                            for (int kk = 0; kk < K; ++kk) {
+                                if constexpr (std::is_same<typename C::RT, float>::value)
+                                    Wv[kk] = I.ring0[slot][kk][I.ringw][I.lane];
+                                else
+                                    Wv[kk] = __uint_as_float((uint32_t)I.ring0[slot][kk][I.ringw][I.lane] << 16);
+                            }
+                        } else {
+#pragma unroll
+                            for (int kk = 0; kk < K; ++kk) Wv[kk] = cr[(j - J0) * R][kk];
+                        }
+                    }
+                    // level j-1: z-queue (registers) and in-plane tile (LDS)
+                    const float* zq = q[j - 1 - B >= 0 ? j - 1 - B : 0];
+                    const float(*T)[XT] = Pt[j - 1];
+                    nbhd<R> n;
+                    n.c = zq[R];
+#pragma unroll
+                    for (int r = 1; r <= R; ++r) {
+                        n.pair[0][r - 1] = T[ylt][xt - r] + T[ylt][xt + r];
+                        n.pair[1][r - 1] = T[ylt - r][xt] + T[ylt + r][xt];
+                        n.pair[2][r - 1] = zq[R - r] + zq[R + r];
+                    }
+                    n.m1[0] = T[ylt][xt - 1];
+                    n.p1[0] = T[ylt][xt + 1];
+                    n.m1[1] = T[ylt - 1][xt];
+                    n.p1[1] = T[ylt + 1][xt];
+                    n.m1[2] = zq[R - 1];
+                    n.p1[2] = zq[R + 1];
+                    float pv = 0.0f;
+                    if constexpr (C::LF) {
+                        // level j-2 at plane z: the old sub for j = jo+1, else
+                        // the oldest entry of level j-2's queue
+                        if (j == JO + 1)
+                            pv = qs[R + 1];
+                        else
+                            pv = q[j - 2 - B >= 0 ? j - 2 - B : 0][0];
+                    }
+                    v = update<C::KIND>(a.wt, Wv, n, pv);
+                    // boundary shell: time independent, from the old-top ring
+                    const bool zin = z >= 0 && z < a.nz;
+                    v = (intr && zin) ? v : sh[(j > JO ? j - JO : 0) * R];
+                }
+                // queue of level j (input of level j+1) or the top queue
+                if (j < J1) {
+                    const int qi = jj + 1 < NL ? jj + 1 : 0;
+#pragma unroll
+                    for (int m = 0; m < Q - 1; ++m) q[qi][m] = q[qi][m + 1];
+                    q[qi][Q - 1] = v;
+                } else {
+#pragma unroll
+                    for (int m = R - 1; m > 0; --m) qt[m] = qt[m - 1];
+                    qt[0] = v;
+                }
+                if (j == jn) vtop = v;
+                if (j == jn - 1) vsub = v;
+                // the slice's edge columns for the neighbours
+                if (j < jn && nex<H>(B) > 0) {
+                    const uint32_t rec = I.my_rec + (seq & (kSlots - 1)) * C::RECB +
+                                         xoff(I, I.eedge > 0 ? 1 : 0, j) + (uint32_t)(I.rr * 4 + I.ecol) * 8u;
+                    u32x2 pk;
+                    pk.x = __float_as_uint(v);
+                    pk.y = I.stamp(seq);
+                    __builtin_amdgcn_raw_buffer_store_b64(pk, I.rX, I.eedge >= 0 ? rec : kNone, 0, kSC1);
+                }
+            }
+        }
+        // new frontier: levels jn and jn-1 of the band's rows, at their planes
+        // (o_ot is at plane s + 2 - (jo - 1) R: two steps ahead)
+        {
+            const int zt = s - (jn - 1) * R;
+            const int zs = jn > jo ? s - (jn - 2) * R : s + 1 - (jo - 1) * R;
+            const uint32_t ot_s = o_ot - 2u * I.sz4;  // plane s - (jo - 1) R
+            const uint32_t st = ot_s - (uint32_t)((jn - jo) * R) * I.sz4;
+            const uint32_t ss = jn > jo ? ot_s - (uint32_t)((jn - 1 - jo) * R) * I.sz4 : ot_s + I.sz4;
+            bstore(I.rNT, vtop, (intr && zt >= I.z0 && zt < I.z1) ? st : kNone, 0u);
+            bstore(I.rNS, vsub, (intr && zs >= I.z0 && zs < I.z1) ? ss : kNone, 0u);
+        }
+    }
+
+    // stage the planes the next step reads in-plane: level l at plane
+    // z_{l+1}(s+1) = s + 1 - l R, the halo columns, the flank rows
+    template <int P>
+    __device__ __forceinline__ void stage(const mwd_item<C>& I, uint32_t seq) {
+        const mwd_kargs& a = *I.a;
+        float(*Pn)[YT][XT] = I.tile[P ^ 1];
+        if constexpr (JO >= 1) Pn[JO - 1][ylt][xt] = qs[0];
+        if constexpr (JO <= L - 1) {
+            if constexpr (JO < J1)
+                Pn[JO][ylt][xt] = q[JO - B][R + 1];
+            else
+                Pn[JO][ylt][xt] = qt[R - 1];
+        }
+#pragma unroll
+        for (int jj = 0; jj < NL; ++jj) {
+            const int l = J0 + jj;
+            if (l > JO && l <= jn && l <= L - 1) {
+                if (l < J1)
+                    Pn[l][ylt][xt] = q[jj + 1 < NL ? jj + 1 : 0][R + 1];
+                else
+                    Pn[l][ylt][xt] = qt[R - 1];
+            }
+        }
+        // halo columns: halo lanes write the tile, the others a spare slot
+        if (jn > JO) *(I.hlane ? &Pn[JO][hty][htc] : I.spare) = p_ht[P];
+        const bool xon = seq + 1 >= (uint32_t)R;
+        const uint32_t want = I.stamp(seq + 1 - R);
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+            const int l = J0 + e;
+            if (nex<H>(B) > 0 && l > jo && l < jn) {
+                uint32_t v = x_v[e];
+                if (__ballot(I.hlane && xon && x_s[e] != want)) {
+                    // late: poll, coherent across the device, until the
+                    // neighbour's value arrives
+                    const uint32_t rec = I.nb_rec + ((seq + 1 - R) & (kSlots - 1)) * C::RECB +
+                                         xoff(I, I.hside ? 0 : 1, l) + (uint32_t)(I.hr * 4 + I.hc) * 8u;
+                    uint32_t got = (I.hlane && xon) ? x_s[e] : want;
+                    // after one failure the run is invalid: do not wait again
+                    int polls = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? kPolls : 0;
+                    while (__ballot(got != want) && polls < kPolls) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (got != want) {
+                            const auto r2 = __builtin_amdgcn_raw_buffer_load_b64(I.rX, rec, 0, kSC1 | kVolatile);
+                            v = r2[0];
+                            got = r2[1];
+                        }
+                        ++polls;
+                    }
+                    if (got != want) atomicOr(a.err, 1);
+                }
+                *(I.hlane ? &Pn[l][hty][htc] : I.spare) = __uint_as_float(v);
+            }
+        }
+        if (B == H - 1 && flank_on) Pn[H - 1][ylf][xt] = p_fl[P];
+        rslot = rslot + 1 == NR0 ? 0 : rslot + 1;
+    }
+};
+
+// The stream of one wave over one item: its one or two bands step together,
+// one barrier per step.
+template <class C, int BA, int BB, int JOA, int JOB, int JNA, int JNB>
+__device__ __forceinline__ void mwd_run(mwd_item<C>& I, uint32_t& seq) {
+    mwd_band<C, BA, JOA, JNA> A;
+    A.init(I);
+    constexpr int BBv = BB >= 0 ? BB : BA;  // (unused when BB < 0)
+    mwd_band<C, BBv, JOB, JNB> Bd;
+    if constexpr (BB >= 0) Bd.init(I);
+    // prefetches run two steps ahead, also past the last step (their loads
+    // are then unused), so that every running offset is two steps ahead of
+    // the step in progress
+    A.template prefetch<0>(I);
+    if constexpr (BB >= 0) Bd.template prefetch<0>(I);
+    A.template prefetch<1>(I);
+    if constexpr (BB >= 0) Bd.template prefetch<1>(I);
+    auto one = [&](int s, auto par) __attribute__((always_inline)) {
+        constexpr int P = decltype(par)::value;
+        A.xload(I, seq);
+        if constexpr (BB >= 0) Bd.xload(I, seq);
+        A.template compute<P>(I, s, seq);
+        if constexpr (BB >= 0) Bd.template compute<P>(I, s, seq);
+        A.template stage<P>(I, seq);
+        if constexpr (BB >= 0) Bd.template stage<P>(I, seq);
+        A.template prefetch<P>(I);
+        if constexpr (BB >= 0) Bd.template prefetch<P>(I);
+        ++seq;
+        __syncthreads();
+    };
+    for (int s = I.s_begin; s < I.s_end; s += 2) {
+        one(s, ic<0>{});
+        if (s + 1 < I.s_end) one(s + 1, ic<1>{});
+    }
+}
+
+template <class C, int BA, int BB>
+__device__ __forceinline__ void mwd_dispatch(mwd_item<C>& I, uint32_t& seq) {
+    constexpr int H = C::H;
+    constexpr int JA = 2 * H - 1 - BA, JB = BB >= 0 ? 2 * H - 1 - BB : 0;
+    if (I.t0 == -H) {
+        // first row: level 0 is the old top of every row, levels 1 .. 2H-1-B
+        // clipped to nt are computed
+        mwd_run<C, BA, BB, H, H, 0, 0>(I, seq);
+    } else if (I.t0 + 2 * H - 1 <= I.nt) {
+        // the rows in between: every level of the diamond
+        mwd_run<C, BA, BB, BA, (BB >= 0 ? BB : BA), JA, JB>(I, seq);
+    } else {
+        // last rows: levels clipped to nt; a band already at nt copies its pair
+        mwd_run<C, BA, BB, BA, (BB >= 0 ? BB : BA), 0, 0>(I, seq);
+    }
+}
+
+template <int KIND, typename CT, int H, int NXW, bool LRING, bool ALN, int CG>
+__global__ __launch_bounds__(4 * NXW * 64) void mwd_row_kernel(mwd_kargs a) {
+    using C = mwd_cfg<KIND, CT, H, NXW, LRING, ALN, CG>;
+    constexpr int R = C::R;
+    __shared__ float tile[2][C::L][C::YT][C::XT];
+    __shared__ float spare[C::NW][64];  // target of lanes with nothing to stage
+    __shared__ typename C::RT ring0[LRING ? C::NR0 : 1][LRING ? C::K : 1][LRING ? 2 * NXW : 1][64];
+
+    mwd_item<C> I;
+    I.a = &a;
+    I.tile = tile;
+    I.ring0 = ring0;
+    I.lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int band = w / (2 * NXW);
-    const int side = (w / NXW) & 1;
-    const int xw = w % NXW;
-    const int cx = lane & 15, rr = lane >> 4;
-
+    const int group = w / (2 * NXW);
+    I.side = (w / NXW) & 1;
+    I.xw = w % NXW;
+    I.ringw = w % (2 * NXW);  // the band-0 waves are group 0
+    I.spare = &spare[w][I.lane];
+    I.cx = I.lane & 15;
+    I.rr = I.lane >> 4;
     // team and slice of this workgroup
     int team, member;
     {
@@ -146,466 +591,77 @@ __global__ __launch_bounds__(2 * H * NXW * 64) void mwd_row_kernel(mwd_kargs a) 
             team = id / a.k;
         }
     }
-    const int x0 = member * XS;
-    const int xl = xw * 16 + cx;  // slice-local column of the lane
-    const int x = x0 + xl;
-    const bool has_left = member > 0, has_right = member < a.k - 1;
+    const int x0 = member * C::XS;
+    I.xl = I.xw * 16 + I.cx;  // slice-local column of the lane
+    I.x = x0 + I.xl;
     // halo lanes: lanes 0..31 of the slice's edge waves carry the R columns
     // beyond the slice (left for xw = 0, right for xw = NXW-1), rows rr
-    const int hside = (lane >> 4) & 1, hr = (lane >> 2) & 3, hc = lane & 3;
-    const bool hlane = lane < 32 && (hside == 0 ? xw == 0 : xw == NXW - 1);
-    const int xh = hside ? x0 + XS + hc : x0 - R + hc;
-    const bool hx_nb = hside ? has_right : has_left;  // halo from a neighbour slice
+    I.hside = (I.lane >> 4) & 1;
+    I.hr = (I.lane >> 2) & 3;
+    I.hc = I.lane & 3;
+    I.hlane = I.lane < 32 && (I.hside == 0 ? I.xw == 0 : I.xw == NXW - 1);
+    I.xh = I.hside ? x0 + C::XS + I.hc : x0 - R + I.hc;
+    I.hx_nb = I.hside ? member < a.k - 1 : member > 0;  // halo from a neighbour slice
     // edge lanes that publish the slice's outer R columns
-    const int eedge = (xw == 0 && cx < 4) ? 0 : ((xw == NXW - 1 && cx >= 12) ? 1 : -1);
-    const int ecol = eedge == 0 ? cx : cx - 12;
-
-    const rsrc_t rX = make_rsrc(a.xbuf, a.xbuf_bytes);
-    const uint32_t my_rec = (uint32_t)(team * a.k + member) * kSlots * RECB;
-    const uint32_t nb_rec = (uint32_t)(team * a.k + member + (hside ? 1 : -1)) * kSlots * RECB;
-
-    uint32_t seq = 0;  // steps done by this workgroup in this launch
-    auto stamp = [&](uint32_t q) { return (a.tag << 20) | (q & 0xfffffu); };
-
-    const int t0 = a.t0, nt = a.nt;
-    auto clampt = [&](int t) { return t < 0 ? 0 : (t > nt ? nt : t); };
-    const uint32_t sz4 = (uint32_t)(a.sz * 4), szc = (uint32_t)(a.sz * CB);
+    I.eedge = (I.xw == 0 && I.cx < 4) ? 0 : ((I.xw == NXW - 1 && I.cx >= 12) ? 1 : -1);
+    I.ecol = I.eedge == 0 ? I.cx : I.cx - 12;
+    I.rX = make_rsrc(a.xbuf, a.xbuf_bytes);
+    I.my_rec = (uint32_t)(team * a.k + member) * kSlots * C::RECB;
+    I.nb_rec = (uint32_t)(team * a.k + member + (I.hside ? 1 : -1)) * kSlots * C::RECB;
+    I.t0 = a.t0;
+    I.nt = a.nt;
+    I.sz4 = (uint32_t)(a.sz * 4);
+    I.szc = (uint32_t)(a.sz * C::CB);
+    I.skb = (uint32_t)((uint64_t)a.sk * C::CB);
     auto nrec = [](uint64_t total, uint64_t off) -> uint32_t {
         const uint64_t r = total > off ? total - off : 0u;
         return (uint32_t)(r < 0x7fffffffull ? r : 0x7fffffffull);
     };
 
+    uint32_t seq = 0;  // steps done by this workgroup in this launch
     for (int it = team; it < a.n_items; it += a.teams) {
         const int di = it / a.gz, zc = it % a.gz;
-        const int yc = a.first_centre + di * DW;
-        const int z0 = zc * a.zchunk;
-        const int z1 = min(a.nz, z0 + a.zchunk);
+        I.yc = a.first_centre + di * C::DW;
+        I.z0 = zc * a.zchunk;
+        I.z1 = min(a.nz, I.z0 + a.zchunk);
         // Level j is needed at planes [z0 - R(L-j), z1 + R(L-j)) (clipped to
         // [-R, nz+R)): the chunk's outputs at level L depend on nothing wider.
         // Every level is computed at every step; values outside a level's
         // window are never read by values inside the windows, so they need no
         // test.  Level 1 starts at its window, after 2R steps that fill the
         // z-queue of the old top.
-        const int s_begin = max(z0 - R * (L - 1), -R) - 2 * R;
-        const int s_end = z1 + (L - 1) * R;
+        I.s_begin = max(I.z0 - R * (C::L - 1), -R) - 2 * R;
+        I.s_end = I.z1 + (C::L - 1) * R;
         // Buffers are based at plane zw, below every plane the item reads, so
         // that 32-bit offsets cover the item's window.  A lane's offset is its
         // row and column plus the plane; it advances by one plane per step.
         // Planes below zw give offsets above 2^31 and planes beyond a buffer
         // offsets beyond its size: both read 0 and store nothing.
-        const int zw = max(z0 - R * (L + 2), -a.hh);
-        const uint64_t fwb = (uint64_t)(zw + a.hh) * (uint64_t)a.sz * 4u;
-        const uint64_t cwb = (uint64_t)(zw + a.hh) * (uint64_t)a.sz * CB;
+        I.zw = max(I.z0 - R * (C::L + 2), -a.hh);
+        const uint64_t fwb = (uint64_t)(I.zw + a.hh) * (uint64_t)a.sz * 4u;
+        const uint64_t cwb = (uint64_t)(I.zw + a.hh) * (uint64_t)a.sz * C::CB;
         const uint32_t fnr = nrec(a.field_bytes, fwb);
-        const rsrc_t rFT = make_rsrc(reinterpret_cast<const char*>(a.ftop_o) + fwb, fnr);
-        const rsrc_t rFS = make_rsrc(reinterpret_cast<const char*>(a.fsub_o) + fwb, fnr);
-        const rsrc_t rNT = make_rsrc(reinterpret_cast<const char*>(a.ftop_n) + fwb, fnr);
-        const rsrc_t rNS = make_rsrc(reinterpret_cast<const char*>(a.fsub_n) + fwb, fnr);
+        I.rFT = make_rsrc(reinterpret_cast<const char*>(a.ftop_o) + fwb, fnr);
+        I.rFS = make_rsrc(reinterpret_cast<const char*>(a.fsub_o) + fwb, fnr);
+        I.rNT = make_rsrc(reinterpret_cast<const char*>(a.ftop_n) + fwb, fnr);
+        I.rNS = make_rsrc(reinterpret_cast<const char*>(a.fsub_n) + fwb, fnr);
         // Coefficient arrays: groups of CG arrays share one resource based at
         // the first array's window and spanning the group (the range check
         // covers the scalar offset too); array k is reached with the scalar
         // offset (k mod CG) * sk bytes, the lane's offset in the vector offset.
         const uint32_t cnr = nrec(a.coef_bytes, cwb);
-        const uint32_t skb = (uint32_t)((uint64_t)a.sk * CB);
-        constexpr int NG = (KG + CG - 1) / CG;
-        rsrc_t rC[NG];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            const int ng = min(CG, KG - g * CG);
-            const uint64_t span = (uint64_t)(ng - 1) * skb + cnr;
-            rC[g] = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<char*>(static_cast<const char*>(a.coef) + (uint64_t)(g * CG) * (uint64_t)a.sk * CB + cwb),
+        for (int g = 0; g < C::NG; ++g) {
+            const int ng = min(C::CG, C::KG - g * C::CG);
+            const uint64_t span = (uint64_t)(ng - 1) * I.skb + cnr;
+            I.rC[g] = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char*>(static_cast<const char*>(a.coef) + (uint64_t)(g * C::CG) * (uint64_t)a.sk * C::CB + cwb),
                 (short)0, (int)(uint32_t)(span < 0xffffffffull ? span : 0xffffffffull), 0x00020000);
         }
-        auto crs = [&](int kk) { return rC[kk / CG]; };
-        auto csoff = [&](int kk) { return (uint32_t)(kk % CG) * skb; };
-        auto plane_off = [&](int z, uint32_t stride) { return (uint32_t)(z - zw) * stride; };
-
-        auto run_band = [&](auto Bc, auto JOc, auto JNc) __attribute__((always_inline)) {
-            constexpr int B = decltype(Bc)::value;
-            constexpr int JO = decltype(JOc)::value;  // old top level: B, or H in the first row
-            constexpr int JN = decltype(JNc)::value;  // new top level if known (> 0)
-            constexpr int J0 = B + 1, J1 = 2 * H - 1 - B;
-            constexpr int NL = J1 - J0 + 1;
-            constexpr bool RL = LRING && B == 0;  // coefficient ring in LDS
-            constexpr int NR = RL ? 1 : (K > 0 ? (NL - 1) * R + 1 : 1);
-            constexpr int KR = (K > 0 && !RL) ? K : 1;
-            constexpr int NSH = (J1 - B) * R + 1;
-            constexpr int NX = nex<H>(B) > 0 ? nex<H>(B) : 1;
-            constexpr int QS = R + 2;
-
-            constexpr int jo = JO;
-            const int jn = JN > 0 ? JN : max(jo, clampt(t0 + J1) - t0);
-            // rows of the band-side, flank rows beyond band H-1
-            const int ybase = side ? yc + B * R : yc - (B + 1) * R;
-            const int y = ybase + rr;
-            const int ylt = side ? (H + 1) * R + B * R + rr : (H - B) * R + rr;  // tile row
-            const int xt = R + xl;                                                 // tile column
-            const bool need = x >= -R && x < a.nx + R && y >= -R && y < a.ny + R;
-            const bool intr = x >= 0 && x < a.nx && y >= 0 && y < a.ny;
-            const uint32_t rc = (uint32_t)((int64_t)(y + a.hh) * a.sy + (x + a.hh));  // element
-            const int yh = ybase + hr;
-            const bool hneed = hlane && xh >= -R && xh < a.nx + R && yh >= -R && yh < a.ny + R;
-            const uint32_t rch = (uint32_t)((int64_t)(yh + a.hh) * a.sy + (xh + a.hh));
-            const int htc = hside ? R + XS + hc : hc;  // tile column of the halo lane
-            const int hty = side ? (H + 1) * R + B * R + hr : (H - B) * R + hr;
-            // flank rows (band H-1 waves): the neighbour diamonds' rows next to this one
-            const int yf = side ? yc + H * R + rr : yc - (H + 1) * R + rr;
-            const int ylf = side ? (2 * H + 1) * R + rr : rr;
-            const bool fneed = B == H - 1 && x >= -R && x < a.nx + R && yf >= -R && yf < a.ny + R;
-            const uint32_t rcf = (uint32_t)((int64_t)(yf + a.hh) * a.sy + (x + a.hh));
-            const int jf = clampt(t0 + H - 1) - t0;
-            const bool flank_on = B == H - 1 && jo == H - 1 && jn >= H && jf == H - 1;
-            // exchange record offsets of this band-side (edge e, level l)
-            auto xoff = [&](int e, int l) {
-                return (uint32_t)(((e * 2 + side) * NEXT + exoff<H>(B) + (l - J0)) * 128);
-            };
-
-            // Per-lane running offsets of the prefetched streams, for the step
-            // the next prefetch is for.  Every offset advances by one plane per
-            // step; a lane that needs nothing starts at kNone and stays at or
-            // above 2^31 (an item's window spans less than 2^31 bytes).
-            const int sp = s_begin;  // first prefetched step
-            uint32_t o_ot = need ? rc * 4u + plane_off(sp - (jo - 1) * R, sz4) : kNone;
-            uint32_t o_ht = (hneed && jn > jo) ? rch * 4u + plane_off(sp + 1 - jo * R, sz4) : kNone;
-            uint32_t o_fl = (fneed && flank_on) ? rcf * 4u + plane_off(sp + 1 - (H - 1) * R, sz4) : kNone;
-            // coefficients of interior points only
-            const int cz0 = RL ? sp : sp - B * R;
-            uint32_t o_c = (need && intr) ? rc * CB + plane_off(cz0, szc) : kNone;
-            // BF16 word loads: the element's half of its 32-bit word is fixed
-            // per lane (even strides, word-aligned arrays)
-            const uint32_t csel = (o_c & 2u) ? 0x03020c0cu : 0x01000c0cu;
-            // band 0's LDS ring slot of the plane it loads at step s
-            int rslot = ((s_begin % NR0) + NR0) % NR0;
-
-            // ---- register state ------------------------------------------
-            float q[NL][Q];      // q[i][.]: level B+i at planes z_{B+i+1} - R .. + R
-            float qt[R];         // level J1, last R steps (qt[0] newest)
-            float qs[QS];        // old sub, last R+2 steps (qs[0] newest)
-            float sh[NSH];       // old-top loads, last NSH steps (sh[0] newest)
-            float cr[NR][KR];    // coefficient ring: cr[i] = plane s - B R - i
-#pragma unroll
-            for (int i = 0; i < NL; ++i)
-#pragma unroll
-                for (int m = 0; m < Q; ++m) q[i][m] = 0.0f;
-#pragma unroll
-            for (int m = 0; m < R; ++m) qt[m] = 0.0f;
-#pragma unroll
-            for (int m = 0; m < QS; ++m) qs[m] = 0.0f;
-#pragma unroll
-            for (int m = 0; m < NSH; ++m) sh[m] = 0.0f;
-#pragma unroll
-            for (int i = 0; i < NR; ++i)
-#pragma unroll
-                for (int kk = 0; kk < KR; ++kk) cr[i][kk] = 0.0f;
-
-            // prefetched operands, two slots
-            float p_ot[2], p_qs[2], p_ht[2], p_fl[2];
-            float p_c[2][KG];
-            uint32_t x_v[NX], x_s[NX];
-
-            const int ringw = w;  // band 0 waves are w = 0 .. 2 NXW - 1
-            auto prefetch = [&](auto slot) __attribute__((always_inline)) {
-                constexpr int SL = decltype(slot)::value;
-                p_ot[SL] = bload(rFT, o_ot, 0u);
-                // the old sub one plane above the old top's
-                p_qs[SL] = (LF || JO >= 1) ? bload(rFS, o_ot + sz4, 0u) : 0.0f;
-                p_ht[SL] = bload(rFT, o_ht, 0u);
-                p_fl[SL] = (B == H - 1) ? bload(rFT, o_fl, 0u) : 0.0f;
-                o_ot += sz4;
-                o_ht += sz4;
-                o_fl += sz4;
-                if constexpr (K > 0) {
-                    if constexpr (ALN) {
-                        uint32_t wv[K];
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk)
-                            wv[kk] = __builtin_amdgcn_raw_buffer_load_b32(crs(kk), o_c & ~3u, csoff(kk), 0);
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk)
-                            p_c[SL][kk] = __uint_as_float(__builtin_amdgcn_perm(wv[kk], wv[kk], csel));
-                    } else {
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk)
-                            p_c[SL][kk] = cload(static_cast<const CT*>(nullptr), crs(kk), o_c, csoff(kk));
-                    }
-                    o_c += szc;
-                }
-            };
-            // halos of the computed levels jo+1 .. jn-1 that the staging at the
-            // end of step s writes: produced by the neighbours at step s+1-R,
-            // loaded at the start of step s (two steps of slack)
-            auto xload = [&]() __attribute__((always_inline)) {
-                const uint32_t slotb = ((seq + 1 - R) & (kSlots - 1)) * RECB;
-                const uint32_t want = stamp(seq + 1 - R);
-#pragma unroll
-                for (int e = 0; e < NX; ++e) {
-                    const int l = J0 + e;
-                    x_v[e] = 0u;
-                    x_s[e] = want;
-                    if (nex<H>(B) > 0 && l > jo && l < jn) {
-                        // from the neighbour slice, or the shell beyond the
-                        // lattice (plane s + 1 - l R) for an edge slice
-                        const uint32_t rec = nb_rec + slotb + xoff(hside ? 0 : 1, l) + (uint32_t)(hr * 4 + hc) * 8u;
-                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rX, (hlane && hx_nb) ? rec : kNone, 0, kSC1);
-                        // o_ht is at plane s + 3 - jo R (two steps ahead)
-                        const uint32_t sv = __builtin_amdgcn_raw_buffer_load_b32(
-                            rFT, (hlane && !hx_nb) ? o_ht - (uint32_t)(2 + (l - jo) * R) * sz4 : kNone, 0u, 0);
-                        x_v[e] = hx_nb ? v[0] : sv;
-                        x_s[e] = hx_nb ? v[1] : want;
-                    }
-                }
-            };
-
-            auto step = [&](int s, auto par) __attribute__((always_inline)) {
-                constexpr int P = decltype(par)::value;
-                xload();
-                const float ot = p_ot[P];
-                // rings
-#pragma unroll
-                for (int m = NSH - 1; m > 0; --m) sh[m] = sh[m - 1];
-                sh[0] = ot;
-#pragma unroll
-                for (int m = QS - 1; m > 0; --m) qs[m] = qs[m - 1];
-                qs[0] = p_qs[P];
-                if constexpr (K > 0) {
-                    if constexpr (RL) {
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk) {
-                            if constexpr (std::is_same<RT, float>::value)
-                                ring0[rslot][kk][ringw][lane] = p_c[P][kk];
-                            else
-                                ring0[rslot][kk][ringw][lane] = (uint16_t)(__float_as_uint(p_c[P][kk]) >> 16);
-                        }
-                    } else {
-#pragma unroll
-                        for (int i = NR - 1; i > 0; --i)
-#pragma unroll
-                            for (int kk = 0; kk < K; ++kk) cr[i][kk] = cr[i - 1][kk];
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk) cr[0][kk] = p_c[P][kk];
-                    }
-                }
-                // the old top enters the queue of level jo (or the top queue)
-                if constexpr (JO < J1) {
-#pragma unroll
-                    for (int m = 0; m < Q - 1; ++m) q[JO - B][m] = q[JO - B][m + 1];
-                    q[JO - B][Q - 1] = ot;
-                }
-                if constexpr (JO == J1) {
-#pragma unroll
-                    for (int m = R - 1; m > 0; --m) qt[m] = qt[m - 1];
-                    qt[0] = ot;
-                }
-                const float(*Pt)[YT][XT] = tile[P];
-                float vtop = ot, vsub = (jn == jo) ? qs[0] : ot;
-#pragma unroll
-                for (int jj = 0; jj < NL; ++jj) {
-                    const int j = J0 + jj;
-                    if (j > JO && j <= jn) {
-                        const int z = s - (j - 1) * R;
-                        float v;
-                        {
-                            float Wv[KS];
-                            Wv[0] = 0.0f;
-                            if constexpr (K > 0) {
-                                if constexpr (RL) {
-                                    int slot = rslot - (j - 1) * R;
-                                    slot = slot < 0 ? slot + NR0 : slot;
-#pragma unroll
-                                    for (int kk = 0; kk < K; ++kk) {
-                                        if constexpr (std::is_same<RT, float>::value)
-                                            Wv[kk] = ring0[slot][kk][ringw][lane];
-                                        else
-                                            Wv[kk] = __uint_as_float((uint32_t)ring0[slot][kk][ringw][lane] << 16);
-                                    }
-                                } else {
-#pragma unroll
-                                    for (int kk = 0; kk < K; ++kk) Wv[kk] = cr[(j - J0) * R][kk];
-                                }
-                            }
-                            // level j-1: z-queue (registers) and in-plane tile (LDS)
-                            const float* zq = q[j - 1 - B >= 0 ? j - 1 - B : 0];
-                            const float(*T)[XT] = Pt[j - 1];
-                            nbhd<R> n;
-                            n.c = zq[R];
-#pragma unroll
-                            for (int r = 1; r <= R; ++r) {
-                                n.pair[0][r - 1] = T[ylt][xt - r] + T[ylt][xt + r];
-                                n.pair[1][r - 1] = T[ylt - r][xt] + T[ylt + r][xt];
-                                n.pair[2][r - 1] = zq[R - r] + zq[R + r];
-                            }
-                            n.m1[0] = T[ylt][xt - 1];
-                            n.p1[0] = T[ylt][xt + 1];
-                            n.m1[1] = T[ylt - 1][xt];
-                            n.p1[1] = T[ylt + 1][xt];
-                            n.m1[2] = zq[R - 1];
-                            n.p1[2] = zq[R + 1];
-                            float pv = 0.0f;
-                            if constexpr (LF) {
-                                // level j-2 at plane z: the old sub for j = jo+1,
-                                // else the oldest entry of level j-2's queue
-                                if (j == JO + 1)
-                                    pv = qs[R + 1];
-                                else
-                                    pv = q[j - 2 - B >= 0 ? j - 2 - B : 0][0];
-                            }
-                            v = update<KIND>(a.wt, Wv, n, pv);
-                            // boundary shell: time independent, from the old-top ring
-                            const bool zin = z >= 0 && z < a.nz;
-                            v = (intr && zin) ? v : sh[(j > JO ? j - JO : 0) * R];
-                        }
-                        // queue of level j (input of level j+1) or the top queue
-                        if (j < J1) {
-                            const int qi = jj + 1 < NL ? jj + 1 : 0;
-#pragma unroll
-                            for (int m = 0; m < Q - 1; ++m) q[qi][m] = q[qi][m + 1];
-                            q[qi][Q - 1] = v;
-                        } else {
-#pragma unroll
-                            for (int m = R - 1; m > 0; --m) qt[m] = qt[m - 1];
-                            qt[0] = v;
-                        }
-                        if (j == jn) vtop = v;
-                        if (j == jn - 1) vsub = v;
-                        // the slice's edge columns for the neighbours
-                        if (j < jn && nex<H>(B) > 0) {
-                            const uint32_t rec = my_rec + (seq & (kSlots - 1)) * RECB +
-                                                 xoff(eedge > 0 ? 1 : 0, j) + (uint32_t)(rr * 4 + ecol) * 8u;
-                            u32x2 pk;
-                            pk.x = __float_as_uint(v);
-                            pk.y = stamp(seq);
-                            __builtin_amdgcn_raw_buffer_store_b64(pk, rX, eedge >= 0 ? rec : kNone, 0, kSC1);
-                        }
-                    }
-                }
-                // new frontier: levels jn and jn-1 of the band's rows, at their planes
-                {
-                    // o_ot is at plane s + 2 - (jo - 1) R (two steps ahead)
-                    const int zt = s - (jn - 1) * R;
-                    const int zs = jn > jo ? s - (jn - 2) * R : s + 1 - (jo - 1) * R;
-                    const uint32_t ot_s = o_ot - 2u * sz4;  // plane s - (jo - 1) R
-                    const uint32_t st = ot_s - (uint32_t)((jn - jo) * R) * sz4;
-                    const uint32_t ss = jn > jo ? ot_s - (uint32_t)((jn - 1 - jo) * R) * sz4 : ot_s + sz4;
-                    bstore(rNT, vtop, (intr && zt >= z0 && zt < z1) ? st : kNone, 0u);
-                    bstore(rNS, vsub, (intr && zs >= z0 && zs < z1) ? ss : kNone, 0u);
-                }
-                // stage the planes the next step reads in-plane: level l at
-                // plane z_{l+1}(s+1) = s + 1 - l R
-                float(*Pn)[YT][XT] = tile[P ^ 1];
-                if constexpr (JO >= 1) Pn[JO - 1][ylt][xt] = qs[0];
-                if constexpr (JO <= L - 1) {
-                    if constexpr (JO < J1)
-                        Pn[JO][ylt][xt] = q[JO - B][R + 1];
-                    else
-                        Pn[JO][ylt][xt] = qt[R - 1];
-                }
-#pragma unroll
-                for (int jj = 0; jj < NL; ++jj) {
-                    const int l = J0 + jj;
-                    if (l > JO && l <= jn && l <= L - 1) {
-                        if (l < J1)
-                            Pn[l][ylt][xt] = q[jj + 1 < NL ? jj + 1 : 0][R + 1];
-                        else
-                            Pn[l][ylt][xt] = qt[R - 1];
-                    }
-                }
-                // halo columns: halo lanes write the tile, the others a spare slot
-                {
-                    if (jn > JO) *(hlane ? &Pn[JO][hty][htc] : &spare[w][lane]) = p_ht[P];
-                    const bool xon = seq + 1 >= (uint32_t)R;
-                    const uint32_t want = stamp(seq + 1 - R);
-#pragma unroll
-                    for (int e = 0; e < NX; ++e) {
-                        const int l = J0 + e;
-                        if (nex<H>(B) > 0 && l > jo && l < jn) {
-                            uint32_t v = x_v[e];
-                            if (__ballot(hlane && xon && x_s[e] != want)) {
-                                // late: poll, coherent across the device, until
-                                // the neighbour's value arrives
-                                const uint32_t rec = nb_rec + ((seq + 1 - R) & (kSlots - 1)) * RECB +
-                                                     xoff(hside ? 0 : 1, l) + (uint32_t)(hr * 4 + hc) * 8u;
-                                uint32_t got = (hlane && xon) ? x_s[e] : want;
-                                // after one failure the run is invalid: do not wait again
-                                int polls = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                                ? kPolls
-                                                : 0;
-                                while (__ballot(got != want) && polls < kPolls) {
-                                    __builtin_amdgcn_s_sleep(1);
-                                    if (got != want) {
-                                        const auto r2 = __builtin_amdgcn_raw_buffer_load_b64(rX, rec, 0, kSC1 | kVolatile);
-                                        v = r2[0];
-                                        got = r2[1];
-                                    }
-                                    ++polls;
-                                }
-                                if (got != want) atomicOr(a.err, 1);
-                            }
-                            *(hlane ? &Pn[l][hty][htc] : &spare[w][lane]) = __uint_as_float(v);
-                        }
-                    }
-                }
-                if (B == H - 1 && flank_on) Pn[H - 1][ylf][xt] = p_fl[P];
-                rslot = rslot + 1 == NR0 ? 0 : rslot + 1;
-                ++seq;
-            };
-
-            // prefetches run two steps ahead, also past the last step (their
-            // loads are then unused), so that every running offset is two
-            // steps ahead of the step in progress
-            prefetch(ic<0>{});
-            prefetch(ic<1>{});
-            for (int s = s_begin; s < s_end; s += 2) {
-                step(s, ic<0>{});
-                prefetch(ic<0>{});
-                __syncthreads();
-                if (s + 1 < s_end) {
-                    step(s + 1, ic<1>{});
-                    prefetch(ic<1>{});
-                    __syncthreads();
-                }
-            }
-        };
-
-        // a band-side whose rows are already at level nt before this row (the
-        // last rows of a run): nothing is computed and no neighbour reads it;
-        // its frontier pair is copied to the new buffers
-        auto copy_band = [&](int B) __attribute__((always_inline)) {
-            const int jo = clampt(t0 + B) - t0;
-            const int y = (side ? yc + B * R : yc - (B + 1) * R) + rr;
-            const bool intr = x >= 0 && x < a.nx && y >= 0 && y < a.ny;
-            const uint32_t rc4 = (uint32_t)((int64_t)(y + a.hh) * a.sy + (x + a.hh)) * 4u;
-            for (int s = s_begin; s < s_end; ++s) {
-                const int zt = s - (jo - 1) * R, zs = s + 1 - (jo - 1) * R;
-                const bool okt = intr && zt >= z0 && zt < z1;
-                const bool oks = intr && zs >= z0 && zs < z1;
-                const uint32_t ot_ = okt ? rc4 + plane_off(zt, sz4) : kNone;
-                const uint32_t os_ = oks ? rc4 + plane_off(zs, sz4) : kNone;
-                bstore(rNT, bload(rFT, ot_, 0u), ot_, 0u);
-                bstore(rNS, bload(rFS, os_, 0u), os_, 0u);
-                ++seq;
-                __syncthreads();
-            }
-        };
-        auto dispatch = [&](auto Bc) __attribute__((always_inline)) {
-            constexpr int B = decltype(Bc)::value;
-            const int jo = clampt(t0 + B) - t0;
-            constexpr int J1 = 2 * H - 1 - B;
-            if (jo == B) {
-                if (t0 + J1 <= nt)
-                    run_band(Bc, ic<B>{}, ic<J1>{});  // every row but the first and last
-                else
-                    run_band(Bc, ic<B>{}, ic<0>{});
-            } else if (jo == H) {
-                run_band(Bc, ic<H>{}, ic<0>{});
-            } else {
-                copy_band(B);
-            }
-        };
-        if constexpr (H >= 1) if (band == 0) dispatch(ic<0>{});
-        if constexpr (H >= 2) if (band == 1) dispatch(ic<1>{});
-        if constexpr (H >= 3) if (band == 2) dispatch(ic<2>{});
-        if constexpr (H >= 4) if (band == 3) dispatch(ic<3>{});
+        if (group == 0)
+            mwd_dispatch<C, gband<H>(0, 0), gband<H>(0, 1)>(I, seq);
+        else
+            mwd_dispatch<C, gband<H>(1, 0), gband<H>(1, 1)>(I, seq);
     }
 }
 
@@ -616,7 +672,7 @@ __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
 
 template <int KIND, typename CT, int H, int NXW, bool LRING, bool ALN, int CG>
 struct mwd_inst {
-    static constexpr int threads = 2 * H * NXW * 64;
+    static constexpr int threads = 4 * NXW * 64;
     static constexpr int XS = 16 * NXW;
     static constexpr uint32_t recb = 2u * 2u * exoff<H>(H) * 16u * 8u;
     static const void* kernel() {
