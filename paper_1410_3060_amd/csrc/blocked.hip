@@ -617,7 +617,17 @@ bool blocked_supported(int kind, int dw) {
 // measured on MI355X over cubes of 64 .. 512: 6 for both 7-point stencils
 // (best or within 10 % of the best at every size); 24 for the radius-4
 // stencils (multi-workgroup diamonds)
-int blocked_default_dw(int kind) { return (kind == 1 || kind == 2) ? 6 : 24; }
+// Measured fastest on the benchmark grids: 16 for the 25-point variable
+// stencil (32-column slices), 32 for the constant leapfrog, 24 for the
+// variable leapfrog.
+int blocked_default_dw(int kind) {
+    switch (kind) {
+    case 3: return 16;
+    case 4: return 32;
+    case 5: return 24;
+    default: return 6;
+    }
+}
 
 int blocked_max_xo(int kind, int dw) {
     const int R = (kind == 1 || kind == 2) ? 1 : 4;

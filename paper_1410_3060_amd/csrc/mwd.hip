@@ -119,6 +119,26 @@ struct mwd_cfg {
     static constexpr int XS = 16 * NXW;
     static constexpr int XT = XS + 2 * R;
     static constexpr int YT = DW + 2 * R;
+    // LDS tile of level l: the rows level l+1 reads, [trlo(l), trlo(l) +
+    // trows(l)) of the YT rows around the diamond, with a pitch of XP floats.
+    // A wave reads 4 rows of 16 columns at a time; XP = 16 (mod 32) puts
+    // them in 4 disjoint 16-bank groups.
+    static constexpr int XP = XT <= 16 ? 16 : ((XT - 16 + 31) / 32) * 32 + 16;
+    static constexpr int tm(int l) { return l < 2 * H - 2 - l ? l : 2 * H - 2 - l; }
+    static constexpr int trlo(int l) { return (H - 1 - tm(l)) * R; }
+    static constexpr int trows(int l) { return (2 * tm(l) + 4) * R; }
+    static constexpr int tbase(int l) {
+        int b = 0;
+        for (int i = 0; i < l; ++i) b += trows(i);
+        return b;
+    }
+    static constexpr int TR = tbase(L);  // rows of all levels
+    // lanes with nothing to stage write a padding column instead (never
+    // read): SPL lanes per row, rows counted across both buffers
+    static constexpr int SPL = XP - XT >= 16 ? 16 : 8;
+    static_assert(XP - XT >= SPL && 4 * NXW_ * 64 / SPL <= 2 * TR, "no room for the staging sink");
+    // flat row of tile row y of level l
+    static constexpr int trow(int l, int y) { return tbase(l) - trlo(l) + y; }
     static constexpr int NR0 = (L - 1) * R + 1;  // coefficient planes of band 0
     static constexpr int NEXT = exoff<H>(H);     // exchanged (band, level) pairs per side
     static constexpr uint32_t RECB = 2u * 2u * NEXT * 16u * 8u;  // bytes per workgroup and slot
@@ -144,9 +164,9 @@ constexpr int gband(int g, int i) {
 template <class C>
 struct mwd_item {
     const mwd_kargs* a;
-    float (*tile)[C::L][C::YT][C::XT];
+    float (*tile)[C::TR][C::XP];
     typename C::RT (*ring0)[C::LRING ? C::K : 1][C::LRING ? 2 * C::NXW : 1][64];
-    float* spare;  // this lane's slot for lanes with nothing to stage
+    float* spare;  // this lane's sink for lanes with nothing to stage (tile padding)
     rsrc_t rFT, rFS, rNT, rNS, rX;
     rsrc_t rC[C::NG];
     uint32_t skb, sz4, szc;
@@ -178,7 +198,6 @@ struct mwd_band {
     static constexpr bool RL = C::LRING && B == 0;  // coefficient ring in LDS
     static constexpr int NR = RL ? 1 : (K > 0 ? (NL - 1) * R + 1 : 1);
     static constexpr int KR = (K > 0 && !RL) ? K : 1;
-    static constexpr int NSH = (J1 - B) * R + 1;
     static constexpr int NX = nex<H>(B) > 0 ? nex<H>(B) : 1;
     static constexpr int QS = R + 2;
     static constexpr int jo = JO;
@@ -191,11 +210,10 @@ struct mwd_band {
     float q[NL][Q];    // q[i][.]: level B+i at planes z_{B+i+1} - R .. + R
     float qt[R];       // level J1, last R steps (qt[0] newest)
     float qs[QS];      // old sub, last R+2 steps (qs[0] newest)
-    float sh[NSH];     // old-top loads, last NSH steps (sh[0] newest)
     float cr[NR][KR];  // coefficient ring: cr[i] = plane s - B R - i
     float p_ot[2], p_qs[2], p_ht[2], p_fl[2];
     float p_c[2][C::KG];
-    uint32_t x_v[NX], x_s[NX];
+    uint32_t x_v[NX], x_s[NX], x_sh[NX];  // exchange loads in flight
 
     __device__ __forceinline__ uint32_t xoff(const mwd_item<C>& I, int e, int l) const {
         return (uint32_t)(((e * 2 + I.side) * C::NEXT + exoff<H>(B) + (l - J0)) * 128);
@@ -252,8 +270,6 @@ struct mwd_band {
 #pragma unroll
         for (int m = 0; m < QS; ++m) qs[m] = 0.0f;
 #pragma unroll
-        for (int m = 0; m < NSH; ++m) sh[m] = 0.0f;
-#pragma unroll
         for (int i = 0; i < NR; ++i)
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) cr[i][kk] = 0.0f;
@@ -289,24 +305,24 @@ struct mwd_band {
 
     // halos of the computed levels jo+1 .. jn-1 that the staging at the end
     // of step s writes: produced by the neighbours at step s+1-R, loaded at
-    // the start of step s (two steps of slack)
+    // the start of step s (two steps of slack).  Only the loads are issued
+    // here; stage() resolves them, so that their latency overlaps the step's
+    // computation.
     __device__ __forceinline__ void xload(const mwd_item<C>& I, uint32_t seq) {
         const uint32_t slotb = ((seq + 1 - R) & (kSlots - 1)) * C::RECB;
-        const uint32_t want = I.stamp(seq + 1 - R);
 #pragma unroll
         for (int e = 0; e < NX; ++e) {
             const int l = J0 + e;
-            x_v[e] = 0u;
-            x_s[e] = want;
             if (nex<H>(B) > 0 && l > jo && l < jn) {
-                // from the neighbour slice, or the shell beyond the lattice
-                // (plane s + 1 - l R; o_ht is two steps ahead) for an edge slice
+                // from the neighbour slice (value and stamp), or the shell
+                // beyond the lattice (plane s + 1 - l R; o_ht is two steps
+                // ahead) for an edge slice
                 const uint32_t rec = I.nb_rec + slotb + xoff(I, I.hside ? 0 : 1, l) + (uint32_t)(I.hr * 4 + I.hc) * 8u;
                 const auto v = __builtin_amdgcn_raw_buffer_load_b64(I.rX, (I.hlane && I.hx_nb) ? rec : kNone, 0, kSC1);
-                const uint32_t sv = __builtin_amdgcn_raw_buffer_load_b32(
+                x_v[e] = v[0];
+                x_s[e] = v[1];
+                x_sh[e] = __builtin_amdgcn_raw_buffer_load_b32(
                     I.rFT, (I.hlane && !I.hx_nb) ? o_ht - (uint32_t)(2 + (l - jo) * R) * I.sz4 : kNone, 0u, 0);
-                x_v[e] = I.hx_nb ? v[0] : sv;
-                x_s[e] = I.hx_nb ? v[1] : want;
             }
         }
     }
@@ -316,9 +332,6 @@ struct mwd_band {
     __device__ __forceinline__ void compute(const mwd_item<C>& I, int s, uint32_t seq) {
         const mwd_kargs& a = *I.a;
         const float ot = p_ot[P];
-#pragma unroll
-        for (int m = NSH - 1; m > 0; --m) sh[m] = sh[m - 1];
-        sh[0] = ot;
 #pragma unroll
         for (int m = QS - 1; m > 0; --m) qs[m] = qs[m - 1];
         qs[0] = p_qs[P];
@@ -351,7 +364,7 @@ struct mwd_band {
             for (int m = R - 1; m > 0; --m) qt[m] = qt[m - 1];
             qt[0] = ot;
         }
-        const float(*Pt)[YT][XT] = I.tile[P];
+        const float(*Pt)[C::XP] = I.tile[P];
         float vtop = ot, vsub = (jn == jo) ? qs[0] : ot;
 #pragma unroll
         for (int jj = 0; jj < NL; ++jj) {
@@ -380,19 +393,20 @@ struct mwd_band {
                     }
                     // level j-1: z-queue (registers) and in-plane tile (LDS)
                     const float* zq = q[j - 1 - B >= 0 ? j - 1 - B : 0];
-                    const float(*T)[XT] = Pt[j - 1];
+                    const float* T = &Pt[C::trow(j - 1, ylt)][xt];  // the lane's point
+                    constexpr int XP = C::XP;
                     nbhd<R> n;
                     n.c = zq[R];
 #pragma unroll
                     for (int r = 1; r <= R; ++r) {
-                        n.pair[0][r - 1] = T[ylt][xt - r] + T[ylt][xt + r];
-                        n.pair[1][r - 1] = T[ylt - r][xt] + T[ylt + r][xt];
+                        n.pair[0][r - 1] = T[-r] + T[r];
+                        n.pair[1][r - 1] = T[-r * XP] + T[r * XP];
                         n.pair[2][r - 1] = zq[R - r] + zq[R + r];
                     }
-                    n.m1[0] = T[ylt][xt - 1];
-                    n.p1[0] = T[ylt][xt + 1];
-                    n.m1[1] = T[ylt - 1][xt];
-                    n.p1[1] = T[ylt + 1][xt];
+                    n.m1[0] = T[-1];
+                    n.p1[0] = T[1];
+                    n.m1[1] = T[-XP];
+                    n.p1[1] = T[XP];
                     n.m1[2] = zq[R - 1];
                     n.p1[2] = zq[R + 1];
                     float pv = 0.0f;
@@ -405,9 +419,11 @@ struct mwd_band {
                             pv = q[j - 2 - B >= 0 ? j - 2 - B : 0][0];
                     }
                     v = update<C::KIND>(a.wt, Wv, n, pv);
-                    // boundary shell: time independent, from the old-top ring
+                    // boundary shell: time independent, so a shell point of
+                    // level j keeps the value it has at level j-1 (which is,
+                    // level by level, the value the old top was loaded with)
                     const bool zin = z >= 0 && z < a.nz;
-                    v = (intr && zin) ? v : sh[(j > JO ? j - JO : 0) * R];
+                    v = (intr && zin) ? v : n.c;
                 }
                 // queue of level j (input of level j+1) or the top queue
                 if (j < J1) {
@@ -451,39 +467,40 @@ struct mwd_band {
     template <int P>
     __device__ __forceinline__ void stage(const mwd_item<C>& I, uint32_t seq) {
         const mwd_kargs& a = *I.a;
-        float(*Pn)[YT][XT] = I.tile[P ^ 1];
-        if constexpr (JO >= 1) Pn[JO - 1][ylt][xt] = qs[0];
+        float(*Pn)[C::XP] = I.tile[P ^ 1];
+        if constexpr (JO >= 1) Pn[C::trow(JO - 1, ylt)][xt] = qs[0];
         if constexpr (JO <= L - 1) {
             if constexpr (JO < J1)
-                Pn[JO][ylt][xt] = q[JO - B][R + 1];
+                Pn[C::trow(JO, ylt)][xt] = q[JO - B][R + 1];
             else
-                Pn[JO][ylt][xt] = qt[R - 1];
+                Pn[C::trow(JO, ylt)][xt] = qt[R - 1];
         }
 #pragma unroll
         for (int jj = 0; jj < NL; ++jj) {
             const int l = J0 + jj;
             if (l > JO && l <= jn && l <= L - 1) {
                 if (l < J1)
-                    Pn[l][ylt][xt] = q[jj + 1 < NL ? jj + 1 : 0][R + 1];
+                    Pn[C::trow(l, ylt)][xt] = q[jj + 1 < NL ? jj + 1 : 0][R + 1];
                 else
-                    Pn[l][ylt][xt] = qt[R - 1];
+                    Pn[C::trow(l, ylt)][xt] = qt[R - 1];
             }
         }
         // halo columns: halo lanes write the tile, the others a spare slot
-        if (jn > JO) *(I.hlane ? &Pn[JO][hty][htc] : I.spare) = p_ht[P];
+        if (jn > JO) *(I.hlane ? &Pn[C::trow(JO, hty)][htc] : I.spare) = p_ht[P];
         const bool xon = seq + 1 >= (uint32_t)R;
         const uint32_t want = I.stamp(seq + 1 - R);
 #pragma unroll
         for (int e = 0; e < NX; ++e) {
             const int l = J0 + e;
             if (nex<H>(B) > 0 && l > jo && l < jn) {
-                uint32_t v = x_v[e];
-                if (__ballot(I.hlane && xon && x_s[e] != want)) {
+                uint32_t v = I.hx_nb ? x_v[e] : x_sh[e];
+                const bool nb = I.hlane && I.hx_nb && xon;
+                if (__ballot(nb && x_s[e] != want)) {
                     // late: poll, coherent across the device, until the
                     // neighbour's value arrives
                     const uint32_t rec = I.nb_rec + ((seq + 1 - R) & (kSlots - 1)) * C::RECB +
                                          xoff(I, I.hside ? 0 : 1, l) + (uint32_t)(I.hr * 4 + I.hc) * 8u;
-                    uint32_t got = (I.hlane && xon) ? x_s[e] : want;
+                    uint32_t got = nb ? x_s[e] : want;
                     // after one failure the run is invalid: do not wait again
                     int polls = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? kPolls : 0;
                     while (__ballot(got != want) && polls < kPolls) {
@@ -497,10 +514,10 @@ struct mwd_band {
                     }
                     if (got != want) atomicOr(a.err, 1);
                 }
-                *(I.hlane ? &Pn[l][hty][htc] : I.spare) = __uint_as_float(v);
+                *(I.hlane ? &Pn[C::trow(l, hty)][htc] : I.spare) = __uint_as_float(v);
             }
         }
-        if (B == H - 1 && flank_on) Pn[H - 1][ylf][xt] = p_fl[P];
+        if (B == H - 1 && flank_on) Pn[C::trow(H - 1, ylf)][xt] = p_fl[P];
         rslot = rslot + 1 == NR0 ? 0 : rslot + 1;
     }
 };
@@ -557,12 +574,24 @@ __device__ __forceinline__ void mwd_dispatch(mwd_item<C>& I, uint32_t& seq) {
     }
 }
 
+// Two workgroups per compute unit where the LDS allows it (no LDS
+// coefficient ring, H <= 3): registers are then capped at 256 per lane.
+template <class C>
+constexpr int mwd_lds_bytes() {
+    return 2 * C::TR * C::XP * 4 + (C::LRING ? C::NR0 * C::K * 2 * C::NXW * 64 * (int)sizeof(typename C::RT) : 0);
+}
+template <class C>
+constexpr int mwd_waves_per_eu() {
+    return (C::H <= 3 && mwd_lds_bytes<C>() <= 80 * 1024) ? 2 : 1;
+}
+
 template <int KIND, typename CT, int H, int NXW, bool LRING, bool ALN, int CG>
-__global__ __launch_bounds__(4 * NXW * 64) void mwd_row_kernel(mwd_kargs a) {
+__global__ __launch_bounds__(4 * NXW * 64)
+__attribute__((amdgpu_waves_per_eu(mwd_waves_per_eu<mwd_cfg<KIND, CT, H, NXW, LRING, ALN, CG>>())))
+void mwd_row_kernel(mwd_kargs a) {
     using C = mwd_cfg<KIND, CT, H, NXW, LRING, ALN, CG>;
     constexpr int R = C::R;
-    __shared__ float tile[2][C::L][C::YT][C::XT];
-    __shared__ float spare[C::NW][64];  // target of lanes with nothing to stage
+    __shared__ float tile[2][C::TR][C::XP];
     __shared__ typename C::RT ring0[LRING ? C::NR0 : 1][LRING ? C::K : 1][LRING ? 2 * NXW : 1][64];
 
     mwd_item<C> I;
@@ -575,7 +604,10 @@ __global__ __launch_bounds__(4 * NXW * 64) void mwd_row_kernel(mwd_kargs a) {
     I.side = (w / NXW) & 1;
     I.xw = w % NXW;
     I.ringw = w % (2 * NXW);  // the band-0 waves are group 0
-    I.spare = &spare[w][I.lane];
+    {
+        const int sr = (w * 64 + I.lane) / C::SPL;  // sink row across both buffers
+        I.spare = &tile[sr / C::TR][sr % C::TR][C::XT + I.lane % C::SPL];
+    }
     I.cx = I.lane & 15;
     I.rr = I.lane >> 4;
     // team and slice of this workgroup
@@ -715,12 +747,14 @@ hipError_t pick_cg(int dw, int nx, team_layout* t) {
     constexpr int R = kR;
     const int H = dw / (2 * R);
     if constexpr (KIND == 3) {
-        if (H == 2) return layout_of<mwd_inst<KIND, CT, 2, 1, false, ALN, CG>>(nx, t);
+        // 32-column slices at H = 2; at H = 3 the LDS coefficient ring of
+        // a 32-column slice would not fit beside the tiles
+        if (H == 2) return layout_of<mwd_inst<KIND, CT, 2, 2, true, ALN, CG>>(nx, t);
         if (H == 3) return layout_of<mwd_inst<KIND, CT, 3, 1, true, ALN, CG>>(nx, t);
     } else {
-        if (H == 2) return layout_of<mwd_inst<KIND, CT, 2, 1, false, ALN, CG>>(nx, t);
-        if (H == 3) return layout_of<mwd_inst<KIND, CT, 3, 1, false, ALN, CG>>(nx, t);
-        if (H == 4) return layout_of<mwd_inst<KIND, CT, 4, 1, false, ALN, CG>>(nx, t);
+        if (H == 2) return layout_of<mwd_inst<KIND, CT, 2, 2, false, ALN, CG>>(nx, t);
+        if (H == 3) return layout_of<mwd_inst<KIND, CT, 3, 2, false, ALN, CG>>(nx, t);
+        if (H == 4) return layout_of<mwd_inst<KIND, CT, 4, 2, false, ALN, CG>>(nx, t);
     }
     return hipErrorInvalidValue;
 }

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 SIZES = {1: (150, 45, 23), 2: (70, 37, 19), 3: (130, 41, 29), 4: (131, 39, 26), 5: (97, 35, 27)}
 # diamond widths per workload: R = 1 for workloads 1 and 3, R = 4 for 2, 4 and 5
-DWS = {1: [8, 4, 12], 2: [24, 16, 32], 3: [8, 4, 12], 4: [24, 16], 5: [24, 16, 32]}
+DWS = {1: [8, 4, 12], 2: [32, 24, 16], 3: [8, 4, 12], 4: [16, 24], 5: [24, 16, 32]}
 
 
 def both(wl, dw, nt, **kw):
@@ -71,9 +71,24 @@ def test_blocked_matches_oracle(index):
 
 @pytest.mark.parametrize("index", [3, 4, 5])
 def test_blocked_bf16_bitwise(index):
-    wl = workloads.make(index, n=SIZES[index], nt=7, coef_dtype="bf16")
-    nb, nb_prev, bl, bl_prev = both(wl, DWS[index][0], 7, zchunk=13)
-    assert_bitwise(bl, nb, f"workload {index} bf16")
+    for dw in DWS[index]:
+        wl = workloads.make(index, n=SIZES[index], nt=7, coef_dtype="bf16")
+        nb, nb_prev, bl, bl_prev = both(wl, dw, 7, zchunk=13)
+        assert_bitwise(bl, nb, f"workload {index} bf16 dw {dw}")
+
+
+@pytest.mark.parametrize("index", [2, 4, 5])
+@pytest.mark.parametrize("nt", [3, 6, 9])
+def test_blocked_radius4_every_width_zchunks(index, nt):
+    """Every provided width of the radius-4 stencils (16-column slices at
+    H = 3 of the 25-point variable stencil, 32-column slices elsewhere) with
+    forced small z-chunks."""
+    for dw in DWS[index][1:]:
+        wl = workloads.make(index, n=SIZES[index], nt=nt)
+        nb, nb_prev, bl, bl_prev = both(wl, dw, nt, zchunk=9)
+        assert_bitwise(bl, nb, f"workload {index} dw {dw} nt {nt}")
+        if nb_prev is not None:
+            assert_bitwise(bl_prev, nb_prev, f"workload {index} dw {dw} nt {nt} (level nt-1)")
 
 
 @pytest.mark.parametrize("index", [1, 4])
