@@ -146,8 +146,14 @@ def main():
     if blocked:
         n_launch = len(st.plan_rows(kind, dw, ny, nt))
         bpl = model.blocked_bytes_per_lup(kind, dw)
-        kname = "blocked_row_kernel<%d, float, H=%d>" % (kind, dw // (2 * model.RADIUS[kind]))
-        tkey = "blocked_row_kernel"
+        H = dw // (2 * model.RADIUS[kind])
+        if model.RADIUS[kind] == 4:
+            # multi-workgroup diamonds (one launch per diamond row)
+            kname = "mwd_row_kernel<%d, float, H=%d>" % (kind, H)
+            tkey = "mwd_row_kernel"
+        else:
+            kname = "blocked_row_kernel<%d, float, H=%d>" % (kind, H)
+            tkey = "blocked_row_kernel"
     else:
         n_launch = nt
         bpl = model.naive_code_balance(kind)
