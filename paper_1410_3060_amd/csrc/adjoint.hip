@@ -20,9 +20,10 @@
 // step m the launch knows lambda_{m+2}, lambda_{m+1} and lambda_m, which are
 // the multipliers of the terms of steps m+1, m and m-1:
 //     g += lambda_{m+2} L8(u_{m+1}) + lambda_{m+1} L8(u_m) + lambda_m L8(u_{m-1})
-// (TERMS selects which are present).  Each L8(u) is evaluated in FP64 from the
-// FP32 values, so that the cancellation inside the stencil sum does not cost
-// FP32 digits in the coefficient gradient.
+// (TERMS selects which are present).  Each L8(u) is formed in FP32 from
+// per-neighbour differences (u(p+r) - u(p)) + (u(p-r) - u(p)), which are exact
+// or nearly so for nearby values, so that the cancellation inside the stencil
+// sum costs no FP32 digits; the products and their sum are FP64.
 //
 // Scaled form (MU).  Where c has no zero, mu = c * lambda obeys
 //     mu_m = 2 mu_{m+1} - mu_{m+2} + c L8(mu_{m+1}),
@@ -43,16 +44,12 @@ namespace {
 constexpr int R = 4;
 constexpr int Q = 2 * R + 1;
 
-struct w64 {
-    double w[5];
-};
-
 // TERMS: bit 0 the term of step m+1, bit 1 of step m, bit 2 of step m-1.
-template <typename CT, int NW, int RPT, int TERMS, bool MU, bool D64>
+template <typename CT, int NW, int RPT, int TERMS, bool MU>
 __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
     const float* __restrict__ lam1, float* lam2, const CT* __restrict__ coef,
     const float* u_p, const float* u_c, const float* u_n, double* __restrict__ g, int nx, int ny,
-    int nz, int64_t sy, int64_t sz, int64_t org, weights wt, w64 wd, int zchunk, int gx, int gy,
+    int nz, int64_t sy, int64_t sz, int64_t org, weights wt, int zchunk, int gx, int gy,
     int ntiles) {
     constexpr int NU = (TERMS & 1) + ((TERMS >> 1) & 1) + ((TERMS >> 2) & 1);
     constexpr int NUA = NU > 0 ? NU : 1;
@@ -61,11 +58,8 @@ __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
     constexpr int LW = 64 + 2 * R;
     constexpr int LH = TY + 2 * R;
     constexpr int HYJ = (2 * R + NW - 1) / NW;
-    // the u planes are staged in FP64 (D64) or FP32: FP64 staging converts
-    // each value once instead of at each of its stencil uses
-    using UT = typename std::conditional<D64, double, float>::type;
     __shared__ float ldv[2][LH][LW];
-    __shared__ UT ldu[NUA][2][LH][LW];
+    __shared__ float ldu[NUA][2][LH][LW];
 
     const int tile = xcd_remap(blockIdx.x, ntiles);
     const int bx = tile % gx;
@@ -244,19 +238,19 @@ __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
             gc[i] = NU > 0 ? gn[i] : 0.0;
             ldv[b][R + wv + NW * i][R + lane] = qv[i][R];
 #pragma unroll
-            for (int f = 0; f < NU; ++f) ldu[f][b][R + wv + NW * i][R + lane] = (UT)qu[f][i][R];
+            for (int f = 0; f < NU; ++f) ldu[f][b][R + wv + NW * i][R + lane] = qu[f][i][R];
         }
 #pragma unroll
         for (int j = 0; j < HYJ; ++j)
             if (wv + NW * j < 2 * R) {
                 ldv[b][hrow[j]][R + lane] = hv[j];
 #pragma unroll
-                for (int f = 0; f < NU; ++f) ldu[f][b][hrow[j]][R + lane] = (UT)hu[f][j];
+                for (int f = 0; f < NU; ++f) ldu[f][b][hrow[j]][R + lane] = hu[f][j];
             }
         if (hx_any) {
             ldv[b][hx_ly][hx_lx] = xv;
 #pragma unroll
-            for (int f = 0; f < NU; ++f) ldu[f][b][hx_ly][hx_lx] = (UT)xu[f];
+            for (int f = 0; f < NU; ++f) ldu[f][b][hx_ly][hx_lx] = xu[f];
         }
         if (z + 1 < z1) fetch(z + 1);
         __syncthreads();
@@ -282,20 +276,24 @@ __global__ __launch_bounds__(NW * 64) void adjoint_step_kernel(
                     if constexpr ((TERMS & 2) != 0) mul[f++] = lam1c;
                     if constexpr ((TERMS & 4) != 0) mul[f++] = lam_m;
                 }
+                // L8(u) from per-neighbour differences, which are exact or
+                // nearly so for nearby values: the cancellation inside the
+                // stencil sum costs no FP32 digits and the value carries about
+                // one FP32 rounding; the products and their sum in FP64
                 double sum = 0.0;
 #pragma unroll
                 for (int f = 0; f < NU; ++f) {
-                    double lu = wd.w[0] * (double)qu[f][i][R];
+                    const float c = qu[f][i][R];
+                    float lu = wt.lres * c;
 #pragma unroll
                     for (int r = 1; r <= R; ++r) {
-                        const double px =
-                            (double)ldu[f][b][ly][lx - r] + (double)ldu[f][b][ly][lx + r];
-                        const double py =
-                            (double)ldu[f][b][ly - r][lx] + (double)ldu[f][b][ly + r][lx];
-                        const double pz = (double)qu[f][i][R - r] + (double)qu[f][i][R + r];
-                        lu = __builtin_fma(wd.w[r], (px + py) + pz, lu);
+                        const float dx = (ldu[f][b][ly][lx - r] - c) + (ldu[f][b][ly][lx + r] - c);
+                        const float dy = (ldu[f][b][ly - r][lx] - c) + (ldu[f][b][ly + r][lx] - c);
+                        const float dz = (qu[f][i][R - r] - c) + (qu[f][i][R + r] - c);
+                        lu = __builtin_fmaf(wt.w[r], (dx + dy) + dz, lu);
                     }
-                    sum = f == 0 ? (double)mul[f] * lu : __builtin_fma((double)mul[f], lu, sum);
+                    sum = f == 0 ? (double)mul[f] * (double)lu
+                                 : __builtin_fma((double)mul[f], (double)lu, sum);
                 }
                 if (cst[i]) G[zo + co[i]] = gc[i] + sum;
             }
@@ -391,48 +389,47 @@ int util_blocks(const dims& d) {
 
 namespace {
 
-template <typename CT, int NW, int RPT, int TERMS, bool MU, bool D64>
+template <typename CT, int NW, int RPT, int TERMS, bool MU>
 hipError_t launch_terms(const float* lam1, float* lam2, const CT* coef, const float* up,
                         const float* uc, const float* un, double* g, const dims& d,
-                        const weights& wt, const w64& wd, int zchunk, hipStream_t s) {
+                        const weights& wt, int zchunk, hipStream_t s) {
     constexpr int TY = NW * RPT;
     const int gx = (d.nx + 63) / 64, gy = (d.ny + TY - 1) / TY;
     if (zchunk <= 0) {
         const long long slots = device_slots(
-            reinterpret_cast<const void*>(&adjoint_step_kernel<CT, NW, RPT, TERMS, MU, D64>),
-            NW * 64);
+            reinterpret_cast<const void*>(&adjoint_step_kernel<CT, NW, RPT, TERMS, MU>), NW * 64);
         zchunk = pick_zchunk(d.nz, (long long)gx * gy, slots, R);
     }
     const int gz = (d.nz + zchunk - 1) / zchunk;
     const long long ntiles = (long long)gx * gy * gz;
     if (ntiles <= 0) return hipSuccess;
     if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((adjoint_step_kernel<CT, NW, RPT, TERMS, MU, D64>), dim3((unsigned)ntiles),
+    hipLaunchKernelGGL((adjoint_step_kernel<CT, NW, RPT, TERMS, MU>), dim3((unsigned)ntiles),
                        dim3(NW * 64), 0,
                        s, lam1, lam2, coef, up, uc, un, g, d.nx, d.ny, d.nz, d.sy, d.sz, d.org(),
-                       wt, wd, zchunk, gx, gy, (int)ntiles);
+                       wt, zchunk, gx, gy, (int)ntiles);
     return hipGetLastError();
 }
 
 template <typename CT, bool MU>
 hipError_t launch_ct(const float* lam1, float* lam2, const CT* coef, const float* up,
                      const float* uc, const float* un, double* g, const dims& d, const weights& wt,
-                     const w64& wd, int zchunk, hipStream_t s) {
+                     int zchunk, hipStream_t s) {
     const int terms = (up ? 1 : 0) | (uc ? 2 : 0) | (un ? 4 : 0);
-#define STN_ADJ_CASE(T, NW, RPT, D64)                                                        \
-    case T:                                                                                  \
-        return launch_terms<CT, NW, RPT, T, MU, D64>(lam1, lam2, coef, up, uc, un, g, d, wt, wd, \
-                                                     zchunk, s)
-    // waves per workgroup, rows per lane and FP64 staging of the u planes by
-    // term set (registers: one 2R+1 queue per stencil field and row)
+#define STN_ADJ_CASE(T, NW, RPT)                                                               \
+    case T:                                                                                    \
+        return launch_terms<CT, NW, RPT, T, MU>(lam1, lam2, coef, up, uc, un, g, d, wt, zchunk, s)
+    // waves per workgroup and rows per lane by term set (registers: one
+    // 2R+1 queue per stencil field and row); measured on the 256^3 leapfrog:
+    // 4 x 2 ahead of 8 x 1, 8 x 2 and 16 x 1
     switch (terms) {
-        STN_ADJ_CASE(0, 4, 4, false);
-        STN_ADJ_CASE(1, 4, 2, false);
-        STN_ADJ_CASE(2, 4, 2, false);
-        STN_ADJ_CASE(3, 4, 2, false);
-        STN_ADJ_CASE(4, 4, 2, false);
-        STN_ADJ_CASE(6, 4, 2, false);
-        STN_ADJ_CASE(7, 4, 2, false);
+        STN_ADJ_CASE(0, 4, 4);
+        STN_ADJ_CASE(1, 4, 2);
+        STN_ADJ_CASE(2, 4, 2);
+        STN_ADJ_CASE(3, 4, 2);
+        STN_ADJ_CASE(4, 4, 2);
+        STN_ADJ_CASE(6, 4, 2);
+        STN_ADJ_CASE(7, 4, 2);
     default: return hipErrorInvalidValue;
     }
 #undef STN_ADJ_CASE
@@ -446,20 +443,16 @@ hipError_t launch_adjoint_step(bool bf16, bool mu, const float* lam1, float* lam
                                int zchunk, hipStream_t s) {
     if ((u_p || u_c || u_n) && !g) return hipErrorInvalidValue;
     weights wt;
-    w64 wd;
-    for (int i = 0; i < 5; ++i) {
-        wt.w[i] = (float)w[i];
-        wd.w[i] = w[i];
-    }
+    for (int i = 0; i < 5; ++i) wt.w[i] = (float)w[i];
     wt.alpha = 1.0f;
     wt.lres = (float)(w[0] + 6.0 * (w[1] + w[2] + w[3] + w[4]));
     const auto* c16 = static_cast<const uint16_t*>(coef);
     const auto* c32 = static_cast<const float*>(coef);
     if (mu)
-        return bf16 ? launch_ct<uint16_t, true>(lam1, lam2, c16, u_p, u_c, u_n, g, d, wt, wd, zchunk, s)
-                    : launch_ct<float, true>(lam1, lam2, c32, u_p, u_c, u_n, g, d, wt, wd, zchunk, s);
-    return bf16 ? launch_ct<uint16_t, false>(lam1, lam2, c16, u_p, u_c, u_n, g, d, wt, wd, zchunk, s)
-                : launch_ct<float, false>(lam1, lam2, c32, u_p, u_c, u_n, g, d, wt, wd, zchunk, s);
+        return bf16 ? launch_ct<uint16_t, true>(lam1, lam2, c16, u_p, u_c, u_n, g, d, wt, zchunk, s)
+                    : launch_ct<float, true>(lam1, lam2, c32, u_p, u_c, u_n, g, d, wt, zchunk, s);
+    return bf16 ? launch_ct<uint16_t, false>(lam1, lam2, c16, u_p, u_c, u_n, g, d, wt, zchunk, s)
+                : launch_ct<float, false>(lam1, lam2, c32, u_p, u_c, u_n, g, d, wt, zchunk, s);
 }
 
 hipError_t launch_scale_copy(float* dst, const float* src, float a, const dims& d, hipStream_t s) {
