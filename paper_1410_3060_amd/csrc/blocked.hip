@@ -1,6 +1,8 @@
-// Temporally blocked scheme: diamond tiles along y, a wavefront streaming
-// along z inside each diamond (Sect. 4.1-4.3: the "CATS2"/1WD form of
-// wavefront diamond blocking; Sect. 5.1: several workers share one diamond).
+// Temporally blocked scheme for the radius-1 stencils (Fig. 1b, 1c): diamond
+// tiles along y, a wavefront streaming along z inside each diamond
+// (Sect. 4.1-4.3: the "CATS2"/1WD form of wavefront diamond blocking;
+// Sect. 5.1: several workers share one diamond).  The radius-4 stencils take
+// the multi-workgroup form in mwd.hip; the entry points below dispatch to it.
 //
 // One launch processes one row of diamonds (the rows of Sect. 4.2 are
 // independent inside, dependent across: the launch boundary is the global
@@ -614,12 +616,10 @@ bool blocked_supported(int kind, int dw) {
     return H >= 2 && H <= 6;
 }
 
-// measured on MI355X over cubes of 64 .. 512: 6 for both 7-point stencils
-// (best or within 10 % of the best at every size); 24 for the radius-4
-// stencils (multi-workgroup diamonds)
-// Measured fastest on the benchmark grids: 16 for the 25-point variable
-// stencil (32-column slices), 32 for the constant leapfrog, 24 for the
-// variable leapfrog.
+// Measured on MI355X: 6 for both 7-point stencils (cubes of 64 .. 512: best
+// or within 10 % of the best at every size); on the benchmark grids 16 for
+// the 25-point variable stencil (32-column slices), 32 for the constant
+// leapfrog, 24 for the variable leapfrog.
 int blocked_default_dw(int kind) {
     switch (kind) {
     case 3: return 16;
