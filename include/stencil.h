@@ -119,7 +119,7 @@ typedef struct {
                             dw >= 4R; provided: 4..12 for R = 1, 16 and 24 for kind 3,
                             16, 24 and 32 for kinds 4-5 (others return
                             STENCIL_ERR_UNSUPPORTED); 0 = the library's choice (6 for
-                            R = 1; 16, 32, 24 for kinds 3, 4, 5) */
+                            R = 1; 16, 32, 16 for kinds 3, 4, 5) */
     int32_t xtile;       /* reserved, 0 */
     int32_t zchunk;      /* planes per z-chunk of one workgroup (parallelism along z);
                             0 = the library's choice */

@@ -618,13 +618,13 @@ bool blocked_supported(int kind, int dw) {
 
 // Measured on MI355X: 6 for both 7-point stencils (cubes of 64 .. 512: best
 // or within 10 % of the best at every size); on the benchmark grids 16 for
-// the 25-point variable stencil (32-column slices), 32 for the constant
-// leapfrog, 24 for the variable leapfrog.
+// the 25-point variable stencil and the variable leapfrog (32-column slices,
+// two workgroups per compute unit), 32 for the constant leapfrog.
 int blocked_default_dw(int kind) {
     switch (kind) {
     case 3: return 16;
     case 4: return 32;
-    case 5: return 24;
+    case 5: return 16;
     default: return 6;
     }
 }

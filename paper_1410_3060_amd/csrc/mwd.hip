@@ -574,15 +574,20 @@ __device__ __forceinline__ void mwd_dispatch(mwd_item<C>& I, uint32_t& seq) {
     }
 }
 
-// Two workgroups per compute unit where the LDS allows it (no LDS
-// coefficient ring, H <= 3): registers are then capped at 256 per lane.
 template <class C>
 constexpr int mwd_lds_bytes() {
     return 2 * C::TR * C::XP * 4 + (C::LRING ? C::NR0 * C::K * 2 * C::NXW * 64 * (int)sizeof(typename C::RT) : 0);
 }
+// Waves per SIMD the registers are sized for: two workgroups per compute unit
+// where the LDS allows it.  At H = 2 with 32-column slices that is 4 (128
+// registers; a few spill to scratch, measured faster: BF16 25-point variable
+// stencil 127 -> 149 GLUP/s, variable leapfrog 198 at dw 16); elsewhere 2
+// (H <= 3) or 1.
 template <class C>
 constexpr int mwd_waves_per_eu() {
-    return (C::H <= 3 && mwd_lds_bytes<C>() <= 80 * 1024) ? 2 : 1;
+    if (mwd_lds_bytes<C>() > 80 * 1024) return 1;
+    if (C::H == 2 && C::NXW == 2) return 4;
+    return C::H <= 3 ? 2 : 1;
 }
 
 template <int KIND, typename CT, int H, int NXW, bool LRING, bool ALN, int CG>

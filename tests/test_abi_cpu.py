@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_default_diamond_widths():
-    assert [st.default_dw(k) for k in (1, 2, 3, 4, 5)] == [6, 6, 16, 32, 24]
+    assert [st.default_dw(k) for k in (1, 2, 3, 4, 5)] == [6, 6, 16, 32, 16]
     assert st.load().stencil_default_dw(9) == 0
     for k in (1, 2, 3, 4, 5):
         R = 1 if k <= 2 else 4
