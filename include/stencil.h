@@ -120,7 +120,12 @@ typedef struct {
                             16, 24 and 32 for kinds 4-5 (others return
                             STENCIL_ERR_UNSUPPORTED); 0 = the library's choice (6 for
                             R = 1; 16, 32, 16 for kinds 3, 4, 5) */
-    int32_t xtile;       /* reserved, 0 */
+    int32_t xtile;       /* x columns per workgroup of the radius-4 blocked scheme: 16 or
+                            32 (32 not at dw 24 of kind 3); each diamond is then shared by
+                            ceil(nx / xtile) cooperating workgroups (Sect. 5.1, thread
+                            groups); 0 = the library's choice (32, or 16 at dw 24 of
+                            kind 3); other values are STENCIL_ERR_INVALID; ignored by
+                            the naive scheme and the radius-1 blocked kernel */
     int32_t zchunk;      /* planes per z-chunk of one workgroup (parallelism along z);
                             0 = the library's choice */
     int32_t ckpt_every;  /* checkpoint interval k recorded by stencil_run() for the kinds
@@ -234,6 +239,13 @@ int stencil_plan_rows(stencil_kind kind, int32_t dw, int32_t ny, int64_t nt, int
    is 0 (Sect. 4.2: a multiple of 2R, at least 4R), or 0 for an unknown kind.
    No HIP call. */
 int32_t stencil_default_dw(stencil_kind kind);
+
+/* Workgroups that share one diamond of the blocked scheme for (kind, dw,
+   xtile, nx) as stencil_tuning would set them (dw 0 and xtile 0 = the
+   library's choices): ceil(nx / slice width) for the radius-4 kinds, 1 for
+   the radius-1 kinds (one workgroup per diamond and x-tile), 0 for a
+   combination that is not provided or a bad argument.  No HIP call. */
+int32_t stencil_blocked_slices(stencil_kind kind, int32_t dw, int32_t xtile, int32_t nx);
 
 #ifdef __cplusplus
 }

@@ -69,7 +69,7 @@ class _Tuning(ctypes.Structure):
 
 EXPORTS = ("stencil_create", "stencil_run", "stencil_run_noalloc", "stencil_adjoint",
            "stencil_sync", "stencil_destroy", "stencil_last_error", "stencil_plan_rows",
-           "stencil_default_dw")
+           "stencil_default_dw", "stencil_blocked_slices")
 
 _lib = None
 
@@ -104,6 +104,9 @@ def load(path: Optional[str] = None):
     lib.stencil_plan_rows.restype = ctypes.c_int
     lib.stencil_default_dw.argtypes = [ctypes.c_int]
     lib.stencil_default_dw.restype = ctypes.c_int32
+    lib.stencil_blocked_slices.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32]
+    lib.stencil_blocked_slices.restype = ctypes.c_int32
     if path is None:
         _lib = lib
     return lib
@@ -175,9 +178,9 @@ class Context:
     """A library context: one scheme, tuning knobs, a borrowed HIP stream."""
 
     def __init__(self, scheme: int = NAIVE, *, dw: int = 0, zchunk: int = 0, ckpt_every: int = 0,
-                 workspace_limit: int = 0, stream=None):
+                 workspace_limit: int = 0, stream=None, xtile: int = 0):
         lib = load()
-        t = _Tuning(dw, 0, zchunk, ckpt_every, workspace_limit)
+        t = _Tuning(dw, xtile, zchunk, ckpt_every, workspace_limit)
         h = ctypes.c_void_p()
         _check(lib.stencil_create(ctypes.byref(h), scheme, ctypes.byref(t),
                                   ctypes.c_void_p(_stream_handle(stream))))
@@ -266,6 +269,12 @@ def default_dw(kind: int) -> int:
     if dw <= 0:
         raise ValueError(f"unknown stencil kind {kind}")
     return dw
+
+
+def blocked_slices(kind: int, dw: int = 0, xtile: int = 0, nx: int = 1) -> int:
+    """Workgroups sharing one diamond of the blocked scheme (``stencil_blocked_slices``):
+    ceil(nx / slice width) for the radius-4 kinds, 1 for radius 1, 0 if not provided."""
+    return int(load().stencil_blocked_slices(kind, dw, xtile, nx))
 
 
 def plan_rows(kind: int, dw: int, ny: int, nt: int):

@@ -310,8 +310,10 @@ int64_t blocked_max_zchunk(int kind, int dw, const stencil_grid* g) {
 // plane below 2^31 bytes (planes below about 2^31 / (2R(L+1) + 2) bytes).
 int check_blocked(const stencil_ctx* ctx, int kind, const stencil_grid* g) {
     const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
-    if (!stn::blocked_supported(kind, dw))
-        return fail(STENCIL_ERR_UNSUPPORTED, "blocked scheme: dw=%d is not provided for kind %d", dw,
+    const int xs = kind_radius(kind) == 4 ? ctx->tuning.xtile : 0;
+    if (!stn::blocked_supported(kind, dw, xs))
+        return fail(STENCIL_ERR_UNSUPPORTED,
+                    "blocked scheme: dw=%d with xtile=%d is not provided for kind %d", dw, xs,
                     kind);
     if (blocked_max_zchunk(kind, dw, g) < 1)
         return fail(STENCIL_ERR_UNSUPPORTED,
@@ -372,9 +374,10 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
         if (e != hipSuccess) return dev_fail(e, "shell copy");
     }
     const bool bf16 = c->dtype == STENCIL_BF16;
-    if (stn::mwd_supported(kind, dw)) {
+    const int xs = ctx->tuning.xtile;
+    if (stn::mwd_supported(kind, dw, xs)) {
         size_t xbytes = 0;
-        e = stn::mwd_workspace(kind, bf16, dw, g->nx, &xbytes);
+        e = stn::mwd_workspace(kind, bf16, dw, xs, g->nx, &xbytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(STENCIL_ERR_UNSUPPORTED,
@@ -411,6 +414,7 @@ int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil
             a.first_centre = row.first_centre;
             a.n_diamonds = row.n_diamonds;
             a.dw = dw;
+            a.xs = xs;
             a.zchunk = ctx->tuning.zchunk;
             a.field_bytes = fbytes;
             a.coef_bytes = FL.span * (bf16 ? 2 : 4);
@@ -919,6 +923,8 @@ int stencil_create(stencil_ctx** out, stencil_scheme scheme, const stencil_tunin
         return fail(STENCIL_ERR_INVALID, "negative tuning value");
     if (t.dw != 0 && (t.dw % 2 != 0 || t.dw < 4))
         return fail(STENCIL_ERR_INVALID, "dw=%d must be even and >= 4", t.dw);
+    if (t.xtile != 0 && t.xtile != 16 && t.xtile != 32)
+        return fail(STENCIL_ERR_INVALID, "xtile=%d must be 0, 16 or 32", t.xtile);
     stencil_ctx* ctx = new (std::nothrow) stencil_ctx();
     if (!ctx) return fail(STENCIL_ERR_NOMEM, "context allocation failed");
     ctx->scheme = scheme;
@@ -1085,6 +1091,14 @@ int32_t stencil_default_dw(stencil_kind kind) {
         return 0;
     }
     return stn::blocked_default_dw(k);
+}
+
+int32_t stencil_blocked_slices(stencil_kind kind, int32_t dw, int32_t xtile, int32_t nx) {
+    const int k = (int)kind;
+    if (k < 1 || k > 5 || nx < 1) return 0;
+    if (kind_radius(k) != 4) return 1;  // one workgroup per diamond and x-tile
+    if (dw == 0) dw = stn::blocked_default_dw(k);
+    return stn::mwd_slices(k, dw, xtile, nx);
 }
 
 int stencil_plan_rows(stencil_kind kind, int32_t dw, int32_t ny, int64_t nt, int64_t* out,

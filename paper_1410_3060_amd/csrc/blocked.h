@@ -50,10 +50,11 @@ constexpr size_t kScratchBytes = size_t(128) << 20;
 hipError_t blocked_scratch(void** ptr);
 
 // Multi-workgroup diamonds for the radius-4 kinds (mwd.hip): one launch per
-// diamond row; teams of workgroups share a diamond, one 16-column x-slice
-// each, exchanging x-halos through `xbuf` (cleared to zero before the first
-// row of a run; `tag` 1 .. 4095 differs between consecutive launches).  A
-// halo that never arrives sets *err to non-zero.
+// diamond row; teams of workgroups share a diamond, one x-slice of xs = 16 or
+// 32 columns each (0 = the default for the width), exchanging x-halos through
+// `xbuf` (cleared to zero before the first row of a run; `tag` 1 .. 4095
+// differs between consecutive launches).  A halo that never arrives sets
+// *err to non-zero.
 struct mwd_row_args {
     const float* ftop_o;
     const float* fsub_o;
@@ -66,6 +67,7 @@ struct mwd_row_args {
     int64_t t0, nt;
     int first_centre, n_diamonds;
     int dw;
+    int xs = 0;      // slice width (columns per workgroup), 0 = default
     int zchunk = 0;  // planes per z-chunk, 0 = chosen from the team count
     uint64_t field_bytes, coef_bytes;
     // BF16 arrays on 4-byte boundaries with even sk and sz: word loads
@@ -75,13 +77,15 @@ struct mwd_row_args {
     int* err;
     uint32_t tag;
 };
-bool mwd_supported(int kind, int dw);
-// bytes of exchange buffer the launches of (kind, dw) need on this device for nx
-hipError_t mwd_workspace(int kind, bool bf16, int dw, int nx, size_t* xbytes);
+bool mwd_supported(int kind, int dw, int xs);
+// workgroups sharing one diamond (x-slices) for nx columns, 0 if not provided
+int mwd_slices(int kind, int dw, int xs, int nx);
+// bytes of exchange buffer the launches of (kind, dw, xs) need on this device for nx
+hipError_t mwd_workspace(int kind, bool bf16, int dw, int xs, int nx, size_t* xbytes);
 hipError_t launch_mwd_row(int kind, bool bf16, const mwd_row_args& a, hipStream_t s);
 hipError_t launch_fill_u32(void* p, size_t words, uint32_t v, hipStream_t s);
 
-bool blocked_supported(int kind, int dw);
+bool blocked_supported(int kind, int dw, int xs = 0);
 int blocked_default_dw(int kind);
 int blocked_max_xo(int kind, int dw);
 hipError_t launch_blocked_row(int kind, bool bf16, const blocked_row_args& a, hipStream_t s);

@@ -609,8 +609,8 @@ hipError_t blocked_scratch(void** ptr) {
     return hipSuccess;
 }
 
-bool blocked_supported(int kind, int dw) {
-    if (kind >= 3) return mwd_supported(kind, dw);
+bool blocked_supported(int kind, int dw, int xs) {
+    if (kind >= 3) return mwd_supported(kind, dw, xs);
     if (dw % 2 != 0) return false;
     const int H = dw / 2;
     return H >= 2 && H <= 6;

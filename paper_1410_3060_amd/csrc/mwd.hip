@@ -747,19 +747,30 @@ hipError_t layout_of(int nx, team_layout* t) {
     return hipSuccess;
 }
 
+// Slice width xs (0 = the default for the width): 32 columns at H = 2, and at
+// H = 3, 4 of the leapfrogs; 16 columns at H = 3 of the 25-point variable
+// stencil, whose LDS coefficient ring for 32 columns would not fit beside the
+// tiles (xs = 32 is not provided there).
 template <int KIND, typename CT, bool ALN, int CG>
-hipError_t pick_cg(int dw, int nx, team_layout* t) {
+hipError_t pick_cg(int dw, int nx, int xs, team_layout* t) {
     constexpr int R = kR;
     const int H = dw / (2 * R);
     if constexpr (KIND == 3) {
-        // 32-column slices at H = 2; at H = 3 the LDS coefficient ring of
-        // a 32-column slice would not fit beside the tiles
-        if (H == 2) return layout_of<mwd_inst<KIND, CT, 2, 2, true, ALN, CG>>(nx, t);
-        if (H == 3) return layout_of<mwd_inst<KIND, CT, 3, 1, true, ALN, CG>>(nx, t);
+        if (H == 2) {
+            if (xs == 16) return layout_of<mwd_inst<KIND, CT, 2, 1, true, ALN, CG>>(nx, t);
+            return layout_of<mwd_inst<KIND, CT, 2, 2, true, ALN, CG>>(nx, t);
+        }
+        if (H == 3 && xs != 32) return layout_of<mwd_inst<KIND, CT, 3, 1, true, ALN, CG>>(nx, t);
     } else {
-        if (H == 2) return layout_of<mwd_inst<KIND, CT, 2, 2, false, ALN, CG>>(nx, t);
-        if (H == 3) return layout_of<mwd_inst<KIND, CT, 3, 2, false, ALN, CG>>(nx, t);
-        if (H == 4) return layout_of<mwd_inst<KIND, CT, 4, 2, false, ALN, CG>>(nx, t);
+        if (xs == 16) {
+            if (H == 2) return layout_of<mwd_inst<KIND, CT, 2, 1, false, ALN, CG>>(nx, t);
+            if (H == 3) return layout_of<mwd_inst<KIND, CT, 3, 1, false, ALN, CG>>(nx, t);
+            if (H == 4) return layout_of<mwd_inst<KIND, CT, 4, 1, false, ALN, CG>>(nx, t);
+        } else {
+            if (H == 2) return layout_of<mwd_inst<KIND, CT, 2, 2, false, ALN, CG>>(nx, t);
+            if (H == 3) return layout_of<mwd_inst<KIND, CT, 3, 2, false, ALN, CG>>(nx, t);
+            if (H == 4) return layout_of<mwd_inst<KIND, CT, 4, 2, false, ALN, CG>>(nx, t);
+        }
     }
     return hipErrorInvalidValue;
 }
@@ -778,42 +789,56 @@ int coef_group(int kind, bool bf16, int64_t sk, uint64_t coef_bytes) {
 }
 
 template <int KIND, typename CT, bool ALN>
-hipError_t pick_aln(int dw, int nx, int cg, team_layout* t) {
+hipError_t pick_aln(int dw, int nx, int xs, int cg, team_layout* t) {
     if constexpr (KIND == 3) {
-        if (cg == 13) return pick_cg<KIND, CT, ALN, 13>(dw, nx, t);
-        if (cg == 7) return pick_cg<KIND, CT, ALN, 7>(dw, nx, t);
+        if (cg == 13) return pick_cg<KIND, CT, ALN, 13>(dw, nx, xs, t);
+        if (cg == 7) return pick_cg<KIND, CT, ALN, 7>(dw, nx, xs, t);
     }
-    return pick_cg<KIND, CT, ALN, 1>(dw, nx, t);
+    return pick_cg<KIND, CT, ALN, 1>(dw, nx, xs, t);
 }
 
 template <int KIND, typename CT>
-hipError_t pick(int dw, int nx, bool aln, int cg, team_layout* t) {
+hipError_t pick(int dw, int nx, int xs, bool aln, int cg, team_layout* t) {
     if constexpr (std::is_same<CT, uint16_t>::value) {
-        if (aln) return pick_aln<KIND, CT, true>(dw, nx, cg, t);
+        if (aln) return pick_aln<KIND, CT, true>(dw, nx, xs, cg, t);
     }
-    return pick_aln<KIND, CT, false>(dw, nx, cg, t);
+    return pick_aln<KIND, CT, false>(dw, nx, xs, cg, t);
 }
 
-hipError_t pick_any(int kind, bool bf16, int dw, int nx, bool aln, int cg, team_layout* t) {
+hipError_t pick_any(int kind, bool bf16, int dw, int nx, int xs, bool aln, int cg,
+                    team_layout* t) {
     switch (kind) {
-    case 3: return bf16 ? pick<3, uint16_t>(dw, nx, aln, cg, t) : pick<3, float>(dw, nx, aln, cg, t);
-    case 4: return pick<4, float>(dw, nx, false, 1, t);
-    case 5: return bf16 ? pick<5, uint16_t>(dw, nx, aln, 1, t) : pick<5, float>(dw, nx, aln, 1, t);
+    case 3:
+        return bf16 ? pick<3, uint16_t>(dw, nx, xs, aln, cg, t)
+                    : pick<3, float>(dw, nx, xs, aln, cg, t);
+    case 4: return pick<4, float>(dw, nx, xs, false, 1, t);
+    case 5:
+        return bf16 ? pick<5, uint16_t>(dw, nx, xs, aln, 1, t)
+                    : pick<5, float>(dw, nx, xs, aln, 1, t);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-bool mwd_supported(int kind, int dw) {
+bool mwd_supported(int kind, int dw, int xs) {
     if (kind < 3 || kind > 5 || dw % (2 * kR) != 0) return false;
+    if (xs != 0 && xs != 16 && xs != 32) return false;
     const int H = dw / (2 * kR);
-    return kind == 3 ? (H == 2 || H == 3) : (H >= 2 && H <= 4);
+    if (kind == 3) return H == 2 || (H == 3 && xs != 32);
+    return H >= 2 && H <= 4;
 }
 
-hipError_t mwd_workspace(int kind, bool bf16, int dw, int nx, size_t* xbytes) {
+int mwd_slices(int kind, int dw, int xs, int nx) {
+    if (!mwd_supported(kind, dw, xs)) return 0;
+    const int H = dw / (2 * kR);
+    const int w = xs ? xs : ((kind == 3 && H == 3) ? 16 : 32);
+    return nx < 1 ? 1 : (nx + w - 1) / w;
+}
+
+hipError_t mwd_workspace(int kind, bool bf16, int dw, int xs, int nx, size_t* xbytes) {
     team_layout t;
-    hipError_t e = pick_any(kind, bf16, dw, nx, false, 1, &t);
+    hipError_t e = pick_any(kind, bf16, dw, nx, xs, false, 1, &t);
     if (e != hipSuccess) return e;
     *xbytes = (size_t)t.teams * t.k * kSlots * t.recb;
     return hipSuccess;
@@ -829,7 +854,7 @@ hipError_t launch_fill_u32(void* p, size_t words, uint32_t v, hipStream_t s) {
 
 hipError_t launch_mwd_row(int kind, bool bf16, const mwd_row_args& r, hipStream_t s) {
     team_layout t;
-    hipError_t e = pick_any(kind, bf16, r.dw, r.d.nx, r.coef_aligned,
+    hipError_t e = pick_any(kind, bf16, r.dw, r.d.nx, r.xs, r.coef_aligned,
                             coef_group(kind, bf16, r.sk, r.coef_bytes), &t);
     if (e != hipSuccess) return e;
     const int R = kR;

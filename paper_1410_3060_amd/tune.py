@@ -17,7 +17,7 @@ from __future__ import annotations
 
 from typing import Dict, Iterable, List, Optional
 
-from . import (BLOCKED, KIND_25PT_WAVE, KIND_7PT_CONST, L8_WEIGHTS, LEAPFROG, NAIVE, NCOEF,
+from . import (BLOCKED, blocked_slices, KIND_25PT_WAVE, KIND_7PT_CONST, L8_WEIGHTS, LEAPFROG, NAIVE, NCOEF,
                RADIUS, Context, alloc_field, default_dw, field_like)
 
 # diamond widths the blocked kernel is compiled for, per stencil radius
@@ -57,7 +57,7 @@ def _weights(kind):
 
 
 def time_run(kind, scheme, n3, nt, *, dw=0, halo=None, coef_dtype="f32", reps=2, seed=1410,
-             inputs=None) -> float:
+             inputs=None, xtile=0) -> float:
     """Median seconds of one complete ``nt``-step run (after one warm-up run),
     HIP events on the current stream."""
     import torch
@@ -67,7 +67,7 @@ def time_run(kind, scheme, n3, nt, *, dw=0, halo=None, coef_dtype="f32", reps=2,
     w, alpha = _weights(kind)
     stream = torch.cuda.current_stream()
     ts: List[float] = []
-    with Context(scheme, dw=dw, stream=stream) as ctx:
+    with Context(scheme, dw=dw, xtile=xtile, stream=stream) as ctx:
         for i in range(reps + 1):
             a.copy_(a0)
             b.copy_(b0)
@@ -84,21 +84,29 @@ def time_run(kind, scheme, n3, nt, *, dw=0, halo=None, coef_dtype="f32", reps=2,
 
 
 def autotune(kind: int, n3, nt: int, *, halo: Optional[int] = None, coef_dtype: str = "f32",
-             reps: int = 2, dws: Optional[Iterable[int]] = None, seed: int = 1410) -> Dict:
+             reps: int = 2, dws: Optional[Iterable[int]] = None, seed: int = 1410,
+             xtiles: Iterable[int] = (0,)) -> Dict:
     """Time the naive sweep and the blocked scheme at every provided diamond
-    width (or ``dws``) for this kind, size and step count; returns
+    width (or ``dws``) and, for the radius-4 kinds, every slice width in
+    ``xtiles`` (0 = the library's choice; 16 and 32 set the workgroups per
+    diamond, ``blocked_slices``) for this kind, size and step count; returns
     ``{"best": {...}, "results": [...]}`` with GLUP/s per candidate.  Pass the
-    best ``dw`` to ``Context(BLOCKED, dw=...)``."""
+    best ``dw`` and ``xtile`` to ``Context(BLOCKED, dw=..., xtile=...)``."""
     h = halo or RADIUS[kind]
     nx, ny, nz = n3
     lups = nx * ny * nz * nt
     inputs = _inputs(kind, n3, h, coef_dtype, seed)
-    cands = [(NAIVE, 0)] + [(BLOCKED, d) for d in (dws or PROVIDED_DW[kind])]
+    xts = list(xtiles) if RADIUS[kind] == 4 else [0]
+    cands = [(NAIVE, 0, 0)] + [(BLOCKED, d, x) for d in (dws or PROVIDED_DW[kind]) for x in xts
+                               if blocked_slices(kind, d, x, nx) > 0]
     results = []
-    for scheme, d in cands:
-        t = time_run(kind, scheme, n3, nt, dw=d, halo=h, reps=reps, inputs=inputs)
+    for scheme, d, x in cands:
+        t = time_run(kind, scheme, n3, nt, dw=d, halo=h, reps=reps, inputs=inputs, xtile=x)
         results.append({"scheme": "naive" if scheme == NAIVE else "blocked",
                         "dw": d if scheme == BLOCKED else None,
+                        "xtile": x if scheme == BLOCKED else None,
+                        "workgroups_per_diamond": blocked_slices(kind, d, x, nx)
+                        if scheme == BLOCKED else None,
                         "seconds": t, "glups": lups / t / 1e9})
     best = max(results, key=lambda r: r["glups"])
     return {"kind": kind, "n": list(n3), "nt": nt, "coef_dtype": coef_dtype,

@@ -45,7 +45,8 @@ def test_struct_layouts_match_header():
 
 def make_ctx(scheme=st.NAIVE, **kw):
     lib = st.load()
-    t = st._Tuning(kw.get("dw", 0), 0, kw.get("zchunk", 0), kw.get("ckpt", 0), kw.get("limit", 0))
+    t = st._Tuning(kw.get("dw", 0), kw.get("xtile", 0), kw.get("zchunk", 0), kw.get("ckpt", 0),
+                   kw.get("limit", 0))
     h = ctypes.c_void_p()
     rc = lib.stencil_create(ctypes.byref(h), scheme, ctypes.byref(t), None)
     return rc, h
@@ -89,6 +90,8 @@ def test_create_validates_tuning():
     assert rc == 1 and "dw" in msg()
     rc, h = make_ctx(zchunk=-1)
     assert rc == 1
+    rc, h = make_ctx(xtile=24)
+    assert rc == 1 and "xtile" in msg()
     rc, h = make_ctx()
     assert rc == 0 and h.value
     st.load().stencil_destroy(h)
@@ -144,6 +147,33 @@ def test_blocked_dw_must_fit_radius():
     assert rc == 0
     g = grid(halo=4)
     assert run(h, 3, g, coeffs(3, g))[0] == 1 and "dw" in msg()
+    st.load().stencil_destroy(h)
+
+
+def test_workgroups_per_diamond():
+    """stencil_blocked_slices: the radius-4 diamonds are shared by ceil(nx /
+    slice width) workgroups (32 columns by default, 16 at dw 24 of the
+    25-point variable stencil); radius 1 keeps one workgroup per diamond and
+    x-tile; combinations that are not provided give 0."""
+    assert st.blocked_slices(3, 16, 0, 480) == 15
+    assert st.blocked_slices(3, 0, 0, 480) == 15       # default dw 16
+    assert st.blocked_slices(3, 16, 16, 480) == 30
+    assert st.blocked_slices(3, 24, 0, 480) == 30
+    assert st.blocked_slices(3, 24, 32, 480) == 0      # no 32-column slice at H = 3
+    assert st.blocked_slices(4, 32, 0, 512) == 16
+    assert st.blocked_slices(5, 24, 16, 250) == 16
+    assert st.blocked_slices(5, 16, 24, 256) == 0      # not a slice width
+    assert st.blocked_slices(4, 40, 0, 512) == 0       # H = 5 not provided
+    assert st.blocked_slices(1, 6, 0, 100) == 1
+    assert st.blocked_slices(9, 16, 0, 100) == 0
+    assert st.blocked_slices(3, 16, 0, 0) == 0
+
+
+def test_blocked_slice_width_checked_before_any_device_call():
+    rc, h = make_ctx(scheme=st.BLOCKED, dw=24, xtile=32)
+    assert rc == 0
+    g = grid(halo=4)
+    assert run(h, 3, g, coeffs(3, g))[0] == 2 and "xtile=32" in msg()
     st.load().stencil_destroy(h)
 
 

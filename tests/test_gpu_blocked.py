@@ -155,6 +155,24 @@ def test_blocked_radius4_other_widths_and_shapes(index):
                     assert_bitwise(bl_prev, nb_prev, f"workload {index} dw {dw} n {n3} nt {nt} prev")
 
 
+@pytest.mark.parametrize("index", [2, 4, 5])
+def test_blocked_radius4_slice_widths(index):
+    """Both slice widths (16 and 32 columns per workgroup, i.e. the
+    workgroups that share a diamond) at every provided diamond width, several
+    slices with a ragged last one, bit-identical to the naive scheme."""
+    n3 = (77, 30, 21)
+    for dw in DWS[index]:
+        for xtile in (16, 32):
+            if st.blocked_slices(workloads.FULL[index]["kind"], dw, xtile, n3[0]) == 0:
+                continue
+            for nt in (3, 7):
+                wl = workloads.make(index, n=n3, nt=nt)
+                nb, nb_prev, bl, bl_prev = both(wl, dw, nt, xtile=xtile)
+                assert_bitwise(bl, nb, f"workload {index} dw {dw} xtile {xtile} nt {nt}")
+                if nb_prev is not None:
+                    assert_bitwise(bl_prev, nb_prev, f"workload {index} dw {dw} xtile {xtile} prev")
+
+
 @pytest.mark.parametrize("index", [3, 4, 5])
 def test_blocked_nonzero_shell(index):
     """A non-zero Dirichlet shell held only by the buffer of level 0 (u[0] for

@@ -20,6 +20,16 @@ def test_autotune_candidates_and_best(kind, n3):
     assert r["library_default_dw"] == st.default_dw(kind)
 
 
+def test_autotune_slice_widths():
+    """The radius-4 candidates at both slice widths: the tuner reports the
+    workgroups that share each diamond (ceil(nx / width)); 32-column slices are
+    not provided at dw 24 of the 25-point variable stencil."""
+    r = tune.autotune(3, (66, 36, 20), 8, reps=1, xtiles=(16, 32))
+    got = [(x["dw"], x["xtile"], x["workgroups_per_diamond"]) for x in r["results"][1:]]
+    assert got == [(16, 16, 5), (16, 32, 3), (24, 16, 5)]
+    assert all(x["glups"] > 0 for x in r["results"])
+
+
 def test_memory_roofs():
     roofs = tune.memory_roofs((4, 64), reps=3)
     assert [x["working_set_MiB"] for x in roofs] == [4, 64]
