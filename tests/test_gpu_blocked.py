@@ -173,6 +173,18 @@ def test_blocked_radius4_slice_widths(index):
                     assert_bitwise(bl_prev, nb_prev, f"workload {index} dw {dw} xtile {xtile} prev")
 
 
+@pytest.mark.parametrize("index,dw,nx", [(2, 32, 1100), (4, 24, 1100), (5, 16, 2100)])
+def test_blocked_radius4_team_across_xcds(index, dw, nx):
+    """A team larger than one XCD holds (33 to 69 slices against 32 or 64
+    resident workgroups per XCD): its slices exchange halos across XCDs
+    through device-coherent stores and loads.  Bit-identical to naive, and
+    no halo waited for in vain (the context reports that as an error)."""
+    print(f"workload {index} dw {dw} nx {nx}", flush=True)
+    wl = workloads.make(index, n=(nx, 20, 12), nt=5)
+    nb, nb_prev, bl, bl_prev = both(wl, dw, 5)
+    assert_bitwise(bl, nb, f"workload {index} dw {dw} nx {nx}")
+
+
 @pytest.mark.parametrize("index", [3, 4, 5])
 def test_blocked_nonzero_shell(index):
     """A non-zero Dirichlet shell held only by the buffer of level 0 (u[0] for
