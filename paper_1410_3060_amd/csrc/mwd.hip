@@ -8,18 +8,19 @@
 // level and again (2H-2)R stream steps later by its last one.  For the
 // 25-point variable-coefficient stencil (13 arrays) the coefficient planes in
 // flight for a diamond of width 24 are about 11 KB per x column: one compute
-// unit holds them for 16 columns, not for a whole row of the lattice.  The
-// paper meets the same wall with its cache (Sect. 5.3, 6.1) and answers it
+// unit holds them for 16 or 32 columns, not for a whole row of the lattice.
+// The paper meets the same wall with its cache (Sect. 5.3, 6.1) and answers it
 // with thread groups sharing a diamond; here a "team" of workgroups shares a
-// diamond, each workgroup owning a 16-column x-slice of every level, so that
-// no column is computed twice.  Neighbouring slices exchange the R columns of
-// each level that the other needs, through device memory.
+// diamond, each workgroup owning an x-slice of 16 or 32 columns of every
+// level, so that no column is computed twice.  Neighbouring slices exchange
+// the R columns of each level that the other needs, through device memory.
 //
 // Inside a workgroup.  Level j (j = 1 .. L = 2H-1, time t0 + j) is produced
 // at plane z_j = s - (j-1)R at stream step s (slope -1/R, Sect. 4.1).  A wave
 // owns one band of R = 4 rows of the diamond (rows whose distance from the
 // centre lies in [B R, (B+1) R)) and 16 columns; band B computes the levels
-// B+1 .. 2H-1-B, each band in its own specialised loop.  A wave keeps per
+// B+1 .. 2H-1-B, each band in its own specialised loop, and each wave runs
+// one or two bands (four waves per 16 columns).  A wave keeps per
 // column the last 2R+1 planes of each level it reads (z-queues in registers)
 // and, where the registers allow, the coefficient planes its levels still
 // need (a register ring; for band 0 of the 13-array stencil the ring is in
@@ -38,7 +39,8 @@
 // reported as failed at the next synchronisation).  Every workgroup of the
 // launch is resident at once (cooperative launch), so every awaited value is
 // eventually written.  Slices of one team are placed on one XCD when the XCD
-// holds a whole team, so the exchange stays in that XCD's L2.
+// holds a whole team, so the exchange stays in that XCD's L2; larger teams
+// span XCDs and rely on the device-coherent path.
 //
 // Rows and launches.  One launch per diamond row; a team processes the
 // row's diamonds (and z-chunks) one after another.  Rows at the start and the
