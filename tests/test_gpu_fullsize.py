@@ -10,7 +10,8 @@ configuration bench.py times (default diamond width, default chunks).
   bounded), every workload, and with BF16 coefficients the parity against the
   oracle on the BF16-rounded values plus the storage error against the oracle
   on the FP32 values;
-* the adjoint of workload 5 (256^3, 200 steps, checkpoints every 14): the
+* the adjoint of workload 5 (256^3, 200 steps, checkpoints every 14): its
+  three gradients element by element against the FP64 oracle adjoint, and the
   dot-product identity <F(d), s> = <d_{-1}, g_{-1}> + <d_0, g_0> for the linear
   map F: (u_{-1}, u_0) -> u_T, which holds at any size.
 """
@@ -137,6 +138,47 @@ def test_fullsize_adjoint_dot_product():
     print(f"adjoint dot product 256^3 nt=200: <F d, s> = {lhs:.9e}, <d, F^T s> = {rhs:.9e}, "
           f"rel {rel:.2e}")
     assert rel <= 1e-5
+
+
+def test_fullsize_adjoint_matches_oracle():
+    """Workload 5 at full size (256^3, 200 steps, checkpoints every 14): the
+    three gradients element by element against the FP64 oracle adjoint run
+    from the same inputs and the same seed (about 30 GB of oracle history)."""
+    import time
+    import torch
+    wl = workloads.make(5)
+    h, nt = wl.halo, wl.nt
+    inner = (slice(h, -h),) * 3
+    c = st.alloc_field(wl.n3, h, count=1)
+    c.copy_(torch.from_numpy(wl.coef))
+    up, u0 = to_dev(wl.u_prev, h), to_dev(wl.u0, h)
+    a, b = to_dev(wl.u_prev, h), to_dev(wl.u0, h)
+    d = to_dev(wl.target, h)
+    with st.Context(st.NAIVE, ckpt_every=workloads.CKPT_EVERY) as ctx:
+        slot = ctx.run(5, a, b, nt, halo=h, coef=c, w=st.L8_WEIGHTS)
+        seed = st.alloc_field(wl.n3, h)
+        seed.copy_((a, b)[slot] - d)
+        g0, gm1 = st.alloc_field(wl.n3, h), st.alloc_field(wl.n3, h)
+        gc = st.alloc_field(wl.n3, h, dtype=torch.float64)
+        ctx.adjoint(up, u0, nt, halo=h, coef=c, w=st.L8_WEIGHTS, seed=seed, grad_u0=g0,
+                    grad_um1=gm1, grad_c=gc)
+        ctx.sync()
+    torch.cuda.synchronize()
+    got = {"um1": host(gm1).astype(np.float64), "u0": host(g0).astype(np.float64),
+           "c": gc.cpu().contiguous().numpy()}
+    sd = host(seed).astype(np.float64)
+    del a, b, d, up, u0, seed, g0, gm1, gc
+    t = time.time()
+    om1, o0, oc = oracle.adjoint_wave_varc(wl.u_prev.astype(np.float64), wl.u0.astype(np.float64),
+                                           wl.coef[0].astype(np.float64), h, nt, sd,
+                                           oracle.l8_weights_3d())
+    print(f"oracle adjoint 256^3 x 200: {time.time() - t:.1f} s")
+    for name, want in (("um1", om1), ("u0", o0), ("c", oc)):
+        g, w = got[name][inner], want[inner]
+        e2 = float(np.linalg.norm((g - w).ravel()) / np.linalg.norm(w.ravel()))
+        em = float(np.abs(g - w).max() / np.abs(w).max())
+        print(f"full-size adjoint grad {name}: rel-L2 {e2:.3e}, max-norm {em:.3e}")
+        assert e2 <= 1e-5 and em <= 1e-4, (name, e2, em)
 
 
 @pytest.mark.parametrize("index", [3, 4])
