@@ -82,6 +82,14 @@ def load(path: Optional[str] = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise ImportError(f"{p} is missing: build it with `python -m paper_1410_3060_amd.build`")
+    # torch ships its own HIP runtime; importing it first lets the library
+    # bind to the runtime already in the process.  Opened before torch, the
+    # library's later HIP calls found no device once torch had initialised
+    # its own.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.stencil_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(_Tuning), vp]

@@ -173,6 +173,33 @@ def test_blocked_radius4_slice_widths(index):
                     assert_bitwise(bl_prev, nb_prev, f"workload {index} dw {dw} xtile {xtile} prev")
 
 
+def test_blocked_radius4_seeded_random_cases():
+    """Seeded random configurations of the radius-4 kernel: shape (1..90 per
+    axis), nt 1..9, every provided width and slice width, FP32 or BF16
+    coefficients, default or forced z-chunks; each bit-identical to naive."""
+    rng = np.random.default_rng([1410, 3060, 7])
+    kinds = {2: 4, 4: 3, 5: 5}
+    done = 0
+    while done < 24:
+        index = int(rng.choice([2, 4, 5]))
+        dw = int(rng.choice(DWS[index]))
+        xtile = int(rng.choice([0, 16, 32]))
+        n3 = tuple(int(v) for v in rng.integers(1, 91, size=3))
+        if st.blocked_slices(kinds[index], dw, xtile, n3[0]) == 0:
+            continue
+        nt = int(rng.integers(1, 10))
+        dtype = "bf16" if index != 2 and rng.random() < 0.4 else "f32"
+        zchunk = int(rng.choice([0, 5, 17]))
+        what = f"workload {index} dw {dw} xtile {xtile} n {n3} nt {nt} {dtype} zchunk {zchunk}"
+        print(what, flush=True)
+        wl = workloads.make(index, n=n3, nt=nt, coef_dtype=dtype)
+        nb, nb_prev, bl, bl_prev = both(wl, dw, nt, xtile=xtile, zchunk=zchunk)
+        assert_bitwise(bl, nb, what)
+        if nb_prev is not None:
+            assert_bitwise(bl_prev, nb_prev, what + " prev")
+        done += 1
+
+
 @pytest.mark.parametrize("index,dw,nx", [(2, 32, 1100), (4, 24, 1100), (5, 16, 2100)])
 def test_blocked_radius4_team_across_xcds(index, dw, nx):
     """A team larger than one XCD holds (33 to 69 slices against 32 or 64
