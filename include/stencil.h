@@ -240,8 +240,8 @@ int stencil_plan_rows(stencil_kind kind, int32_t dw, int32_t ny, int64_t nt, int
    No HIP call. */
 int32_t stencil_default_dw(stencil_kind kind);
 
-/* Workgroups that share one diamond of the blocked scheme for (kind, dw,
-   xtile, nx) as stencil_tuning would set them (dw 0 and xtile 0 = the
+/* Workgroups that share one diamond of the blocked scheme (the thread group
+   of Sect. 5.1) for (kind, dw, xtile, nx) as stencil_tuning would set them (dw 0 and xtile 0 = the
    library's choices): ceil(nx / slice width) for the radius-4 kinds, 1 for
    the radius-1 kinds (one workgroup per diamond and x-tile), 0 for a
    combination that is not provided or a bad argument.  No HIP call. */
