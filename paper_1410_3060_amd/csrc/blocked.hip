@@ -246,6 +246,38 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                t <= nt;
     };
 
+    // Steps of the fast range (every level z_j = s - (j-1)R inside [0, nz)
+    // and inside its active window, see run) read operands whose need
+    // depends on the row alone: the lane offset of each such load (kNone
+    // where the row does not need it) and its plane's offset from plane s
+    // are fixed here, so a fast step forms a load's offset with one add.
+    // An unneeded load keeps a valid plane, so kNone + offset stays below
+    // 2^32 and beyond the buffer.
+    uint32_t ft_v[CPT], fs_v[CPT], fh_v[CPT], fc_v[CPT];
+    uint32_t ft_p[CPT], fs_p[CPT], fh_p[CPT], fl_p[CPT], f0_p[CPT], fp_p[CPT];
+    uint32_t fl_v[CPT], f0_v[CPT], fp_v[CPT];
+    bool f0_sub[CPT];
+    const uint32_t pf0 = pf(0);
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const bool intr = rt[c] == 2;
+        // (the plane offset must stay uniform across the wave: it is the
+        // load's scalar offset)
+        auto off = [&](bool ok, int d, uint32_t& v, uint32_t& p) {
+            v = ok ? vf[c] : kNone;
+            p = ok ? pf0 + (uint32_t)d * sz4 : pf0;
+        };
+        off(intr && jo[c] <= L, (1 - jo[c]) * R, ft_v[c], ft_p[c]);
+        off(intr && jo[c] >= 1 && jo[c] <= L + 1, (2 - jo[c]) * R, fs_v[c], fs_p[c]);
+        fh_v[c] = (rt[c] == 1 || (intr && xb && !xin[c])) ? vf[c] : kNone;
+        fh_p[c] = pf0 + (uint32_t)R * sz4;
+        off(intr && jo[c] == 0 && jn[c] >= 1, 0, fl_v[c], fl_p[c]);
+        off(rt[c] >= 1, 1, f0_v[c], f0_p[c]);
+        off(intr && jo[c] == 1 && jn[c] >= 2, -R, fp_v[c], fp_p[c]);
+        f0_sub[c] = intr && jo[c] == 1;
+        fc_v[c] = (intr && own[c] && jn[c] > jo[c]) ? vc[c] : kNone;
+    }
+
     // ---- register state -------------------------------------------------------
     // qv[j][c][i] = level j at plane z_j - 2R + i (level 0 has none with G0)
     float qv[L][CPT][Q];
@@ -322,17 +354,40 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             }
         }
     };
+    // the same loads for a step s of the fast range
+    const uint32_t pc0 = pc_(0);
+    auto prefetch_fast = [&](int s, auto slot) __attribute__((always_inline)) {
+        constexpr int SL = decltype(slot)::value;
+        const uint32_t sf = (uint32_t)s * sz4;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            pt[SL][c] = bload(rFT, ft_v[c], sf + ft_p[c]);
+            ps[SL][c] = bload(rFS, fs_v[c], sf + fs_p[c]);
+            if constexpr (LF) pl[SL][c] = bload(rFS, fl_v[c], sf + fl_p[c]);
+            if constexpr (G0) {
+                p0[SL][c] = bload(f0_sub[c] ? rFS : rFT, f0_v[c], sf + f0_p[c]);
+                if constexpr (LF) pp[SL][c] = bload(rFS, fp_v[c], sf + fp_p[c]);
+            }
+            ph[SL][c] = bload(rFT, fh_v[c], sf + fh_p[c]);
+            if constexpr (CRING) {
+                const uint32_t so = pc0 + (uint32_t)s * szc;
+#pragma unroll
+                for (int k = 0; k < KR; ++k) pc[SL][c][k] = cload_early(coef, crs(k), fc_v[c], so);
+            }
+        }
+    };
 
     const int s_begin = z0 - R * (L + 1);
     const int s_end = z1 + R * (L - 1);
 
-    // mode 0: interior tile; 1: tile reaching the x boundary; 2: interior tile
+    // mode 0: interior tile; 1: tile reaching the x boundary; 2, 3: the same
     // at a step whose levels are all active and inside [0, nz) (no z logic)
+    // and whose prefetched step is one too
     auto step = [&](int s, auto par, auto mode) __attribute__((always_inline)) {
         constexpr int set = decltype(par)::value;  // LDS set read by step s
         constexpr int SL = PD == 2 ? set : 0;      // prefetch slot holding step s
-        constexpr bool XB = decltype(mode)::value == 1;
-        constexpr bool FAST = decltype(mode)::value == 2;
+        constexpr bool XB = decltype(mode)::value % 2 == 1;
+        constexpr bool FAST = decltype(mode)::value >= 2;
         float ft[CPT], fs[CPT], fl[CPT], f0n[CPT], fp[CPT];
         const int zh = s + R;
         const bool inzh = zh >= 0 && zh < nz;
@@ -477,7 +532,9 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                     lds[set ^ 1][j - 1][lidx[c]] = (G0 && j == 1) ? f0n[c] : qv[j - 1][c][R + 1];
         // operands of a later step, issued after this step's work so that no
         // wait inside it covers them
-        if constexpr (PD == 2) {
+        if constexpr (FAST) {
+            prefetch_fast(s + PD, ic<PD == 2 ? SL : 0>{});
+        } else if constexpr (PD == 2) {
             if (s + 2 < s_end) prefetch(s + 2, ic<SL>{});
         } else {
             if (s + 1 < s_end) prefetch(s + 1, ic<0>{});
@@ -486,25 +543,26 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
     };
 
     auto run = [&](auto mode) __attribute__((always_inline)) {
+        constexpr int M = decltype(mode)::value;
         prefetch(s_begin, ic<0>{});
         if (PD == 2 && s_begin + 1 < s_end) prefetch(s_begin + 1, ic<PD - 1>{});
         int s = s_begin;
-        if constexpr (decltype(mode)::value == 0) {
-            // steps in [f_lo, f_hi) put every level z_j = s - (j-1)R inside
-            // [0, nz) and inside its active window; they run in pairs that keep
-            // the LDS and prefetch parity of the stream
-            const int f_lo = max(z0, 0) + (L - 1) * R;
-            const int f_hi = min(s_end, nz - R);
-            const int s_a = s_begin + 2 * ((max(f_lo - s_begin, 0) + 1) / 2);
-            const int s_b = s_a + 2 * (max(f_hi - s_a, 0) / 2);
-            for (; s < s_a && s < s_end; s += 2) {
-                step(s, ic<0>{}, ic<0>{});
-                if (s + 1 < s_end) step(s + 1, ic<1>{}, ic<0>{});
-            }
-            for (; s < s_b; s += 2) {
-                step(s, ic<0>{}, ic<2>{});
-                step(s + 1, ic<1>{}, ic<2>{});
-            }
+        // steps in [f_lo, f_hi) put every level z_j = s - (j-1)R, j = 0 .. L,
+        // inside [0, nz) and inside its active window; they run in pairs that
+        // keep the LDS and prefetch parity of the stream, the last pair ending
+        // two steps before s_b so that the steps they prefetch (at most s + 3)
+        // lie in the range too
+        const int f_lo = max(z0, 0) + (L - 1) * R;
+        const int f_hi = min(s_end, nz - R);
+        const int s_a = s_begin + 2 * ((max(f_lo - s_begin, 0) + 1) / 2);
+        const int s_b = s_a + 2 * (max(f_hi - s_a, 0) / 2);
+        for (; s < s_a && s < s_end; s += 2) {
+            step(s, ic<0>{}, mode);
+            if (s + 1 < s_end) step(s + 1, ic<1>{}, mode);
+        }
+        for (; s + 2 < s_b; s += 2) {
+            step(s, ic<0>{}, ic<M + 2>{});
+            step(s + 1, ic<1>{}, ic<M + 2>{});
         }
         for (; s < s_end; s += 2) {
             step(s, ic<0>{}, mode);
