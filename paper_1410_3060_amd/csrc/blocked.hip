@@ -108,6 +108,15 @@ __device__ __forceinline__ float cload(const uint16_t*, const coef_rsrc& c, uint
     return __uint_as_float(adj ? (w & 0xffff0000u) : (w << 16));
 }
 
+// A copy of a wave-uniform value that the compiler cannot move out of a
+// loop: a test against it stays a compare at its use instead of a lane mask
+// kept (or spilled) across the loop.
+__device__ __forceinline__ int opaque_s(int v) {
+    int r;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(r) : "s"(v));
+    return r;
+}
+
 template <int KIND, typename CT, int H, int NWV, int XCH, bool CRING, bool G0, int PD, bool WIN,
           bool ALN>
 __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
@@ -412,103 +421,145 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                 for (int k = 0; k < KR; ++k) cr[c][0][k] = pc[SL][c][k];
             }
         }
-        float vt[CPT], vs[CPT];
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) vt[c] = vs[c] = 0.0f;
-#pragma unroll
-        for (int j = 0; j <= L; ++j) {
-            const int z = s - (j - 1) * R;
-            // in the fast range a level outside [-1, nt] in time is treated as
-            // active: no row computes it or reads it, so its values are unused
-            const bool act = FAST || level_active(j, z);
-            const bool zin = FAST || (z >= 0 && z < nz);
+        // level j of column slot c at plane z_j, computed from level j-1
+        auto level_update = [&](int c, int j, const float* P) __attribute__((always_inline)) {
             const int jq = j >= 1 ? j - 1 : 0;
-            const float* P = lds[set][jq];
+            float Wv[kslots<KIND>];
+            Wv[0] = 0.0f;
+            if constexpr (K > 0) {
+                if constexpr (CRING) {
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                float v = 0.0f;
-                if (rt[c] != 0 && act) {
-                    const float shv = sh[c][j * R];
-                    if (rt[c] == 1 || !zin) {
-                        // boundary shell (time independent)
-                        v = shv;
+                    for (int k = 0; k < K; ++k) Wv[k] = cr[c][jq * R][k];
+                } else {
+                    const uint32_t so = pc_(s - (j - 1) * R);
+                    if constexpr (ALN) {
+                        uint32_t wv[K];
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            wv[k] = __builtin_amdgcn_raw_buffer_load_b32(crs(k).r, vw[c], so, 0);
+                        // keep the K loads in flight together (otherwise the
+                        // words share a register and load one at a time)
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            Wv[k] = __uint_as_float(__builtin_amdgcn_perm(wv[k], wv[k], vsel[c]));
                     } else {
-                        v = (j == jo[c]) ? ft[c] : ((j == jo[c] - 1) ? fs[c] : 0.0f);
-                        if (j >= 1 && j > jo[c] && j <= jn[c]) {
-                            float Wv[kslots<KIND>];
-                            Wv[0] = 0.0f;
-                            if constexpr (K > 0) {
-                                if constexpr (CRING) {
 #pragma unroll
-                                    for (int k = 0; k < K; ++k) Wv[k] = cr[c][jq * R][k];
-                                } else {
-                                    const uint32_t so = pc_(z);
-                                    if constexpr (ALN) {
-                                        uint32_t wv[K];
-#pragma unroll
-                                        for (int k = 0; k < K; ++k)
-                                            wv[k] = __builtin_amdgcn_raw_buffer_load_b32(crs(k).r, vw[c], so, 0);
-                                        // keep the K loads in flight together (otherwise the
-                                        // words share a register and load one at a time)
-                                        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                                        for (int k = 0; k < K; ++k)
-                                            Wv[k] = __uint_as_float(__builtin_amdgcn_perm(wv[k], wv[k], vsel[c]));
-                                    } else {
-#pragma unroll
-                                        for (int k = 0; k < K; ++k) Wv[k] = cload(coef, crs(k), vc[c], so);
-                                    }
-                                }
-                            }
-                            float pv = 0.0f;
-                            if constexpr (LF) {
-                                if (j == 1)
-                                    pv = fl[c];
-                                else if (G0 && j == 2)
-                                    pv = jo[c] == 0 ? sh[c][2 * R] : fp[c];
-                                else
-                                    pv = qv[j >= 2 ? j - 2 : 0][c][0];
-                            }
-                            float zq[Q];
-                            if (G0 && j == 1) {
-                                // level 0 (the old frontier top here: jo = 0)
-                                // at planes z - R .. z + R, from the shell ring
-#pragma unroll
-                                for (int i = 0; i < Q; ++i) zq[i] = sh[c][2 * R - i];
-                            } else {
-#pragma unroll
-                                for (int i = 0; i < Q; ++i) zq[i] = qv[jq][c][i];
-                            }
-                            const int li = lidx[c];
-                            nbhd<R> n;
-                            n.c = zq[R];
-#pragma unroll
-                            for (int r = 1; r <= R; ++r) {
-                                n.pair[0][r - 1] = P[li - r] + P[li + r];
-                                n.pair[1][r - 1] = P[li - r * XT] + P[li + r * XT];
-                                n.pair[2][r - 1] = zq[R - r] + zq[R + r];
-                            }
-                            n.m1[0] = P[li - 1];
-                            n.p1[0] = P[li + 1];
-                            n.m1[1] = P[li - XT];
-                            n.p1[1] = P[li + XT];
-                            n.m1[2] = zq[R - 1];
-                            n.p1[2] = zq[R + 1];
-                            v = update<KIND>(wt, Wv, n, pv);
-                        }
-                        if constexpr (XB) {
-                            // columns outside [0, nx) hold the shell at every level
-                            v = xin[c] ? v : shv;
-                        }
+                        for (int k = 0; k < K; ++k) Wv[k] = cload(coef, crs(k), vc[c], so);
                     }
                 }
-                if (j == jn[c]) vt[c] = v;
-                if (j == jn[c] - 1) vs[c] = v;
-                if (j < L && !(G0 && j == 0)) {
-                    const int jw = j < L ? j : 0;
+            }
+            float pv = 0.0f;
+            if constexpr (LF) {
+                if (j == 1)
+                    pv = fl[c];
+                else if (G0 && j == 2)
+                    pv = jo[c] == 0 ? sh[c][2 * R] : fp[c];
+                else
+                    pv = qv[j >= 2 ? j - 2 : 0][c][0];
+            }
+            float zq[Q];
+            if (G0 && j == 1) {
+                // level 0 (the old frontier top here: jo = 0)
+                // at planes z - R .. z + R, from the shell ring
 #pragma unroll
-                    for (int i = 0; i < Q - 1; ++i) qv[jw][c][i] = qv[jw][c][i + 1];
-                    qv[jw][c][Q - 1] = v;
+                for (int i = 0; i < Q; ++i) zq[i] = sh[c][2 * R - i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) zq[i] = qv[jq][c][i];
+            }
+            const int li = lidx[c];
+            nbhd<R> n;
+            n.c = zq[R];
+#pragma unroll
+            for (int r = 1; r <= R; ++r) {
+                n.pair[0][r - 1] = P[li - r] + P[li + r];
+                n.pair[1][r - 1] = P[li - r * XT] + P[li + r * XT];
+                n.pair[2][r - 1] = zq[R - r] + zq[R + r];
+            }
+            n.m1[0] = P[li - 1];
+            n.p1[0] = P[li + 1];
+            n.m1[1] = P[li - XT];
+            n.p1[1] = P[li + XT];
+            n.m1[2] = zq[R - 1];
+            n.p1[2] = zq[R + 1];
+            return update<KIND>(wt, Wv, n, pv);
+        };
+        auto push = [&](int c, int j, float v) __attribute__((always_inline)) {
+            if (j < L && !(G0 && j == 0)) {
+                const int jw = j < L ? j : 0;
+#pragma unroll
+                for (int i = 0; i < Q - 1; ++i) qv[jw][c][i] = qv[jw][c][i + 1];
+                qv[jw][c][Q - 1] = v;
+            }
+        };
+        float vt[CPT], vs[CPT];
+        if constexpr (FAST) {
+            // Every level is active and inside [0, nz): an interior row holds
+            // the old sub and top at levels jo-1 and jo, computes jo+1 .. jn
+            // in order, and no row reads its levels below jo-1 or above jn
+            // (those take any value); a shell row holds the shell at every
+            // level.  The row's type and levels are re-read each step
+            // (opaque_s) so that each test is one compare where it is used.
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int rq = opaque_s(rt[c]), joq = opaque_s(jo[c]), jnq = opaque_s(jn[c]);
+                float top = ft[c], sub = fs[c];
+                if (rq == 2) {
+#pragma unroll
+                    for (int j = 0; j <= L; ++j) {
+                        // (jo >= 0: level 0 is never computed)
+                        float v;
+                        if (j == 0 || j <= joq) {
+                            v = j == joq ? ft[c] : fs[c];
+                            if constexpr (XB) v = xin[c] ? v : sh[c][j * R];
+                        } else if (j <= jnq) {
+                            v = level_update(c, j, lds[set][j >= 1 ? j - 1 : 0]);
+                            // columns outside [0, nx) hold the shell at every level
+                            if constexpr (XB) v = xin[c] ? v : sh[c][j * R];
+                            sub = top;
+                            top = v;
+                        } else {
+                            v = 0.0f;
+                        }
+                        push(c, j, v);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j <= L; ++j) push(c, j, rq == 1 ? sh[c][j * R] : 0.0f);
+                }
+                vt[c] = top;
+                vs[c] = sub;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) vt[c] = vs[c] = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= L; ++j) {
+                const int z = s - (j - 1) * R;
+                const bool act = level_active(j, z);
+                const bool zin = z >= 0 && z < nz;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    float v = 0.0f;
+                    if (rt[c] != 0 && act) {
+                        const float shv = sh[c][j * R];
+                        if (rt[c] == 1 || !zin) {
+                            // boundary shell (time independent)
+                            v = shv;
+                        } else {
+                            v = (j == jo[c]) ? ft[c] : ((j == jo[c] - 1) ? fs[c] : 0.0f);
+                            if (j >= 1 && j > jo[c] && j <= jn[c])
+                                v = level_update(c, j, lds[set][j >= 1 ? j - 1 : 0]);
+                            if constexpr (XB) {
+                                // columns outside [0, nx) hold the shell at every level
+                                v = xin[c] ? v : shv;
+                            }
+                        }
+                    }
+                    if (j == jn[c]) vt[c] = v;
+                    if (j == jn[c] - 1) vs[c] = v;
+                    push(c, j, v);
                 }
             }
         }
