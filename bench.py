@@ -105,7 +105,7 @@ def main():
     lups = nx * ny * nz * nt
     leapfrog = kind in (4, 5)
     w = wl.w if kind == 1 else (st.L8_WEIGHTS if leapfrog else ())
-    dw = args.dw or st.default_dw(kind)
+    dw = args.dw or st.default_dw(kind, wl.n3)
 
     def upload(a):
         t = st.alloc_field(wl.n3, h)
@@ -540,7 +540,7 @@ def config_leg(st, workloads, model, torch, np, stream, index, cpu_seconds, reps
         cf = st.alloc_field(wl.n3, h, count=wl.coef.shape[0])
         cf.copy_(torch.from_numpy(wl.coef))
     a, b = st.field_like(a0, h), st.field_like(b0, h)
-    dw = st.default_dw(kind)
+    dw = st.default_dw(kind, wl.n3)
     out = {"workload": wl.name, "dw": dw}
     fin = {}
     for scheme, name in ((st.NAIVE, "naive"), (st.BLOCKED, "blocked")):

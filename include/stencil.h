@@ -118,8 +118,10 @@ typedef struct {
     int32_t dw;          /* diamond width in y for STENCIL_BLOCKED: a multiple of 2R with
                             dw >= 4R; provided: 4..12 for R = 1, 16 and 24 for kind 3,
                             16, 24 and 32 for kinds 4-5 (others return
-                            STENCIL_ERR_UNSUPPORTED); 0 = the library's choice (6 for
-                            R = 1; 16, 32, 16 for kinds 3, 4, 5) */
+                            STENCIL_ERR_UNSUPPORTED); 0 = the library's choice,
+                            stencil_default_dw() (6 for R = 1, but 10 for kind 2 with
+                            FP32 coefficients on grids of 256^3 points or more; 16, 32,
+                            16 for kinds 3, 4, 5) */
     int32_t xtile;       /* x columns per workgroup of the radius-4 blocked scheme: 16 or
                             32 (32 not at dw 24 of kind 3); each diamond is then shared by
                             ceil(nx / xtile) cooperating workgroups (Sect. 5.1, thread
@@ -236,9 +238,14 @@ int stencil_plan_rows(stencil_kind kind, int32_t dw, int32_t ny, int64_t nt, int
                       int32_t cap);
 
 /* The diamond width the blocked scheme uses for `kind` when stencil_tuning.dw
-   is 0 (Sect. 4.2: a multiple of 2R, at least 4R), or 0 for an unknown kind.
+   is 0 (Sect. 4.2: a multiple of 2R, at least 4R) on an nx x ny x nz grid with
+   coefficients stored as `coef_dtype` (ignored by the kinds without arrays),
+   chosen from measured rates (Sect. 5.3 models the same trade-off between the
+   bytes a wider diamond saves and the block it has to hold); 0 for an unknown
+   kind, a negative size or an unknown dtype (stencil_last_error says which).
    No HIP call. */
-int32_t stencil_default_dw(stencil_kind kind);
+int32_t stencil_default_dw(stencil_kind kind, int32_t nx, int32_t ny, int32_t nz,
+                           stencil_dtype coef_dtype);
 
 /* Workgroups that share one diamond of the blocked scheme (the thread group
    of Sect. 5.1) for (kind, dw, xtile, nx) as stencil_tuning would set them (dw 0 and xtile 0 = the

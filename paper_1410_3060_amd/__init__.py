@@ -110,7 +110,7 @@ def load(path: Optional[str] = None):
     lib.stencil_last_error.restype = ctypes.c_char_p
     lib.stencil_plan_rows.argtypes = [ctypes.c_int, i32, i32, i64, ctypes.POINTER(i64), i32]
     lib.stencil_plan_rows.restype = ctypes.c_int
-    lib.stencil_default_dw.argtypes = [ctypes.c_int]
+    lib.stencil_default_dw.argtypes = [ctypes.c_int, i32, i32, i32, ctypes.c_int]
     lib.stencil_default_dw.restype = ctypes.c_int32
     lib.stencil_blocked_slices.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int32]
@@ -271,11 +271,16 @@ class Context:
         _check(load().stencil_sync(self._h))
 
 
-def default_dw(kind: int) -> int:
-    """Diamond width the blocked scheme uses for `kind` when none is given."""
-    dw = load().stencil_default_dw(kind)
+def default_dw(kind: int, n3=(0, 0, 0), coef_dtype: str = "f32") -> int:
+    """Diamond width the blocked scheme uses for `kind` when none is given, on a
+    grid of interior size n3 = (nx, ny, nz) with coefficients stored as
+    ``coef_dtype`` ("f32" or "bf16"; ``stencil_default_dw``)."""
+    if coef_dtype not in ("f32", "bf16"):
+        raise ValueError(f"coef_dtype must be 'f32' or 'bf16', not {coef_dtype!r}")
+    nx, ny, nz = (int(v) for v in n3)
+    dw = load().stencil_default_dw(kind, nx, ny, nz, 1 if coef_dtype == "bf16" else 0)
     if dw <= 0:
-        raise ValueError(f"unknown stencil kind {kind}")
+        raise ValueError(load().stencil_last_error().decode(errors="replace"))
     return dw
 
 

@@ -305,11 +305,20 @@ int64_t blocked_max_zchunk(int kind, int dw, const stencil_grid* g) {
     return (int64_t)0x7fffffff / plane - 2LL * R * (L + 1) - 1;
 }
 
+// Diamond width of a blocked run: the context's, else the library's choice
+// for the grid's size and the coefficients' storage.
+int blocked_dw(const stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c) {
+    if (ctx->tuning.dw) return ctx->tuning.dw;
+    const bool bf16 = c && c->dtype == STENCIL_BF16;
+    return stn::blocked_default_dw(kind, (int64_t)g->nx * g->ny * g->nz, bf16);
+}
+
 // Limits of the blocked scheme, checked with the other arguments before any
 // HIP call: a provided diamond width, and an address window of one z-chunk
 // plane below 2^31 bytes (planes below about 2^31 / (2R(L+1) + 2) bytes).
-int check_blocked(const stencil_ctx* ctx, int kind, const stencil_grid* g) {
-    const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
+int check_blocked(const stencil_ctx* ctx, int kind, const stencil_grid* g,
+                  const stencil_coeffs* c) {
+    const int dw = blocked_dw(ctx, kind, g, c);
     const int xs = kind_radius(kind) == 4 ? ctx->tuning.xtile : 0;
     if (!stn::blocked_supported(kind, dw, xs))
         return fail(STENCIL_ERR_UNSUPPORTED,
@@ -335,7 +344,7 @@ int check_blocked(const stencil_ctx* ctx, int kind, const stencil_grid* g) {
 int run_blocked(stencil_ctx* ctx, int kind, const stencil_grid* g, const stencil_coeffs* c,
                 int64_t nt, void* frontier, void* xchg = nullptr, size_t xcap = 0) {
     const int R = kind_radius(kind);
-    const int dw = ctx->tuning.dw ? ctx->tuning.dw : stn::blocked_default_dw(kind);
+    const int dw = blocked_dw(ctx, kind, g, c);
     const int H = dw / (2 * R);
     const int L = 2 * H - 1;
     const stn::dims d = to_dims(g);
@@ -958,7 +967,7 @@ int stencil_run(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* grid,
         return STENCIL_OK;
     }
     if (ctx->scheme == STENCIL_BLOCKED) {
-        rc = check_blocked(ctx, k, grid);
+        rc = check_blocked(ctx, k, grid, coeffs);
         if (rc) return rc;
     }
     rc = set_device(ctx);
@@ -1001,7 +1010,7 @@ int stencil_run_noalloc(stencil_ctx* ctx, stencil_kind kind, const stencil_grid*
         if (result_slot) *result_slot = slot;
         return STENCIL_OK;
     }
-    rc = check_blocked(ctx, k, grid);
+    rc = check_blocked(ctx, k, grid, coeffs);
     if (rc) return rc;
     const size_t need = layout_of(grid).bytes(2);
     if (need > stn::kScratchBytes)
@@ -1043,7 +1052,7 @@ int stencil_adjoint(stencil_ctx* ctx, stencil_kind kind, const stencil_grid* gri
     if (empty(grid)) return STENCIL_OK;
     if (ctx->scheme == STENCIL_BLOCKED) {
         // a missing recording is rebuilt with the context's (blocked) forward
-        rc = check_blocked(ctx, k, grid);
+        rc = check_blocked(ctx, k, grid, coeffs);
         if (rc) return rc;
     }
     rc = set_device(ctx);
@@ -1084,20 +1093,25 @@ void stencil_destroy(stencil_ctx* ctx) {
     delete ctx;
 }
 
-int32_t stencil_default_dw(stencil_kind kind) {
+int32_t stencil_default_dw(stencil_kind kind, int32_t nx, int32_t ny, int32_t nz,
+                           stencil_dtype coef_dtype) {
     const int k = (int)kind;
     if (k < 1 || k > 5) {
         fail(STENCIL_ERR_INVALID, "unknown stencil kind %d", k);
         return 0;
     }
-    return stn::blocked_default_dw(k);
+    if (nx < 0 || ny < 0 || nz < 0 || (coef_dtype != STENCIL_F32 && coef_dtype != STENCIL_BF16)) {
+        fail(STENCIL_ERR_INVALID, "bad grid size or coefficient storage");
+        return 0;
+    }
+    return stn::blocked_default_dw(k, (int64_t)nx * ny * nz, coef_dtype == STENCIL_BF16);
 }
 
 int32_t stencil_blocked_slices(stencil_kind kind, int32_t dw, int32_t xtile, int32_t nx) {
     const int k = (int)kind;
     if (k < 1 || k > 5 || nx < 1) return 0;
     if (kind_radius(k) != 4) return 1;  // one workgroup per diamond and x-tile
-    if (dw == 0) dw = stn::blocked_default_dw(k);
+    if (dw == 0) dw = stn::blocked_default_dw(k, 0, false);  // radius 4: independent of both
     return stn::mwd_slices(k, dw, xtile, nx);
 }
 

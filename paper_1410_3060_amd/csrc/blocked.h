@@ -86,7 +86,9 @@ hipError_t launch_mwd_row(int kind, bool bf16, const mwd_row_args& a, hipStream_
 hipError_t launch_fill_u32(void* p, size_t words, uint32_t v, hipStream_t s);
 
 bool blocked_supported(int kind, int dw, int xs = 0);
-int blocked_default_dw(int kind);
+// the diamond width used when none is given, for a grid of `points` interior
+// points and FP32 or BF16 coefficients
+int blocked_default_dw(int kind, int64_t points, bool bf16);
 int blocked_max_xo(int kind, int dw);
 hipError_t launch_blocked_row(int kind, bool bf16, const blocked_row_args& a, hipStream_t s);
 

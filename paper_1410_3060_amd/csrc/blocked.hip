@@ -680,7 +680,7 @@ hipError_t launch_kind(const blocked_row_args& a, hipStream_t s) {
         if (H == 2) return launch_cfg<KIND, CT, 2, 6, 1, true>(a, s);
         if (H == 3) return launch_cfg<KIND, CT, 3, 8, 1, true, true, 2>(a, s);
         if (H == 4) return launch_cfg<KIND, CT, 4, 10, 1, true>(a, s);
-        if (H == 5) return launch_cfg<KIND, CT, 5, 12, 1, true, false, 1>(a, s);
+        if (H == 5) return launch_cfg<KIND, CT, 5, 12, 1, true, true, 2>(a, s);
         if (H == 6) return launch_cfg<KIND, CT, 6, 14, 1, true, false, 1>(a, s);
     }
     return hipErrorInvalidValue;
@@ -725,12 +725,16 @@ bool blocked_supported(int kind, int dw, int xs) {
     return H >= 2 && H <= 6;
 }
 
-// Measured on MI355X: 6 for both 7-point stencils (cubes of 64 .. 512: best
-// or within 10 % of the best at every size); on the benchmark grids 16 for
-// the 25-point variable stencil and the variable leapfrog (32-column slices,
-// two workgroups per compute unit), 32 for the constant leapfrog.
-int blocked_default_dw(int kind) {
+// Measured on MI355X (cubes of 64 .. 512, 100 steps): 6 for the 7-point
+// constant stencil and for the 7-point variable one with BF16 coefficients or
+// below 256^3 points; 10 for the 7-point variable one with FP32 coefficients
+// from 256^3 points on (equal at 256^3, 1.13-1.25x the rate of 6 at 320^3 ..
+// 512^3, where 12 waves share a diamond's levels).  On the benchmark grids 16
+// for the 25-point variable stencil and the variable leapfrog (32-column
+// slices, two workgroups per compute unit), 32 for the constant leapfrog.
+int blocked_default_dw(int kind, int64_t points, bool bf16) {
     switch (kind) {
+    case 2: return (!bf16 && points >= 256LL * 256 * 256) ? 10 : 6;
     case 3: return 16;
     case 4: return 32;
     case 5: return 16;

@@ -110,7 +110,7 @@ def autotune(kind: int, n3, nt: int, *, halo: Optional[int] = None, coef_dtype: 
                         "seconds": t, "glups": lups / t / 1e9})
     best = max(results, key=lambda r: r["glups"])
     return {"kind": kind, "n": list(n3), "nt": nt, "coef_dtype": coef_dtype,
-            "library_default_dw": default_dw(kind), "best": best, "results": results}
+            "library_default_dw": default_dw(kind, n3, coef_dtype), "best": best, "results": results}
 
 
 def memory_roofs(sizes_mib: Iterable[float] = (2, 8, 32, 64, 128, 256, 512, 1024, 4096),

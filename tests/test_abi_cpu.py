@@ -8,6 +8,7 @@ import re
 import pytest
 
 import paper_1410_3060_amd as st
+from paper_1410_3060_amd import tune
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 FAKE = 0x10000  # never dereferenced: validation happens before any device call
@@ -28,12 +29,28 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_default_diamond_widths():
-    assert [st.default_dw(k) for k in (1, 2, 3, 4, 5)] == [6, 6, 16, 32, 16]
-    assert st.load().stencil_default_dw(9) == 0
+    small, large = (64, 64, 64), (512, 512, 512)
+    assert [st.default_dw(k, small) for k in (1, 2, 3, 4, 5)] == [6, 6, 16, 32, 16]
+    assert [st.default_dw(k, large) for k in (1, 2, 3, 4, 5)] == [6, 10, 16, 32, 16]
+    # the 7-point variable stencil: 10 from 256^3 points on, FP32 coefficients only
+    assert st.default_dw(2, (256, 256, 256)) == 10
+    assert st.default_dw(2, (255, 256, 256)) == 6
+    assert st.default_dw(2, large, "bf16") == 6
+    assert st.default_dw(3, large, "bf16") == 16
+    lib = st.load()
+    assert lib.stencil_default_dw(9, 8, 8, 8, 0) == 0
+    assert lib.stencil_default_dw(2, -1, 8, 8, 0) == 0
+    assert lib.stencil_default_dw(2, 8, 8, 8, 7) == 0
+    assert b"coefficient storage" in lib.stencil_last_error()
+    with pytest.raises(ValueError):
+        st.default_dw(2, small, "f16")
     for k in (1, 2, 3, 4, 5):
         R = 1 if k <= 2 else 4
-        dw = st.default_dw(k)
-        assert dw % (2 * R) == 0 and dw >= 4 * R
+        for n3 in (small, large):
+            for dt in ("f32", "bf16"):
+                dw = st.default_dw(k, n3, dt)
+                assert dw % (2 * R) == 0 and dw >= 4 * R
+                assert tune.PROVIDED_DW[k].count(dw) == 1
 
 
 def test_struct_layouts_match_header():

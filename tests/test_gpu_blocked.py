@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 SIZES = {1: (150, 45, 23), 2: (70, 37, 19), 3: (130, 41, 29), 4: (131, 39, 26), 5: (97, 35, 27)}
 # diamond widths per workload: R = 1 for workloads 1 and 3, R = 4 for 2, 4 and 5
-DWS = {1: [8, 4, 12], 2: [32, 24, 16], 3: [8, 4, 12], 4: [16, 24], 5: [16, 24, 32]}
+DWS = {1: [8, 4, 12], 2: [32, 24, 16], 3: [8, 4, 12, 10, 6], 4: [16, 24], 5: [16, 24, 32]}
 
 
 def both(wl, dw, nt, **kw):

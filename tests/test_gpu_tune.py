@@ -17,7 +17,7 @@ def test_autotune_candidates_and_best(kind, n3):
     assert [x["dw"] for x in r["results"][1:]] == list(widths)
     assert all(x["glups"] > 0 for x in r["results"])
     assert r["best"]["glups"] == max(x["glups"] for x in r["results"])
-    assert r["library_default_dw"] == st.default_dw(kind)
+    assert r["library_default_dw"] == st.default_dw(kind, n3)
 
 
 def test_autotune_slice_widths():
