@@ -119,9 +119,9 @@ typedef struct {
                             dw >= 4R; provided: 4..12 for R = 1, 16 and 24 for kind 3,
                             16, 24 and 32 for kinds 4-5 (others return
                             STENCIL_ERR_UNSUPPORTED); 0 = the library's choice,
-                            stencil_default_dw() (6 for R = 1, but 10 for kind 2 with
-                            FP32 coefficients on grids of 256^3 points or more; 16, 32,
-                            16 for kinds 3, 4, 5) */
+                            stencil_default_dw() (6 for R = 1, but 10 for kind 2 on
+                            grids of at least 256^3 points with FP32 coefficients and
+                            300^3 with BF16 ones; 16, 32, 16 for kinds 3, 4, 5) */
     int32_t xtile;       /* x columns per workgroup of the radius-4 blocked scheme: 16 or
                             32 (32 not at dw 24 of kind 3); each diamond is then shared by
                             ceil(nx / xtile) cooperating workgroups (Sect. 5.1, thread

@@ -86,17 +86,22 @@ __device__ __forceinline__ float cload(const float*, const coef_rsrc& c, uint32_
                                        uint32_t soff) {
     return bload(c.r, voff, soff);
 }
-// (prefetched coefficients, read steps before their use, take 16-bit loads;
-// coefficients read in a level's update take the word loads below)
-__device__ __forceinline__ float cload_early(const float*, const coef_rsrc& c, uint32_t voff,
-                                             uint32_t soff) {
+// Prefetched coefficients, read steps before their use, take 16-bit loads
+// and stay raw (the stored bits) until cexpand where they enter the ring: an
+// expansion next to the load would make the wave wait for the load there.
+// Coefficients read in a level's update take the word loads below.
+__device__ __forceinline__ float cload_raw(const float*, const coef_rsrc& c, uint32_t voff,
+                                           uint32_t soff) {
     return bload(c.r, voff, soff);
 }
-__device__ __forceinline__ float cload_early(const uint16_t*, const coef_rsrc& c, uint32_t voff,
-                                             uint32_t soff) {
+__device__ __forceinline__ float cload_raw(const uint16_t*, const coef_rsrc& c, uint32_t voff,
+                                           uint32_t soff) {
     const uint32_t vo = voff >= kNone ? voff : voff + c.mis;
-    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(c.r, vo, soff, 0))
-                           << 16);
+    return __uint_as_float(static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(c.r, vo, soff, 0)));
+}
+__device__ __forceinline__ float cexpand(const float*, float raw) { return raw; }
+__device__ __forceinline__ float cexpand(const uint16_t*, float raw) {
+    return __uint_as_float(__float_as_uint(raw) << 16);
 }
 __device__ __forceinline__ float cload(const uint16_t*, const coef_rsrc& c, uint32_t voff,
                                        uint32_t soff) {
@@ -359,7 +364,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
                                  s >= z0 - R * (L - 1) && s < z1 + R * (L - 1);
 #pragma unroll
                 for (int k = 0; k < KR; ++k)
-                    pc[SL][c][k] = cload_early(coef, crs(k), okc ? vc[c] : kNone, okc ? pc_(s) : 0u);
+                    pc[SL][c][k] = cload_raw(coef, crs(k), okc ? vc[c] : kNone, okc ? pc_(s) : 0u);
             }
         }
     };
@@ -381,7 +386,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
             if constexpr (CRING) {
                 const uint32_t so = pc0 + (uint32_t)s * szc;
 #pragma unroll
-                for (int k = 0; k < KR; ++k) pc[SL][c][k] = cload_early(coef, crs(k), fc_v[c], so);
+                for (int k = 0; k < KR; ++k) pc[SL][c][k] = cload_raw(coef, crs(k), fc_v[c], so);
             }
         }
     };
@@ -418,7 +423,7 @@ __global__ __launch_bounds__(NWV * 64) void blocked_row_kernel(
 #pragma unroll
                     for (int k = 0; k < KR; ++k) cr[c][i][k] = cr[c][i - 1][k];
 #pragma unroll
-                for (int k = 0; k < KR; ++k) cr[c][0][k] = pc[SL][c][k];
+                for (int k = 0; k < KR; ++k) cr[c][0][k] = cexpand(coef, pc[SL][c][k]);
             }
         }
         // level j of column slot c at plane z_j, computed from level j-1
@@ -726,15 +731,16 @@ bool blocked_supported(int kind, int dw, int xs) {
 }
 
 // Measured on MI355X (cubes of 64 .. 512, 100 steps): 6 for the 7-point
-// constant stencil and for the 7-point variable one with BF16 coefficients or
-// below 256^3 points; 10 for the 7-point variable one with FP32 coefficients
-// from 256^3 points on (equal at 256^3, 1.13-1.25x the rate of 6 at 320^3 ..
-// 512^3, where 12 waves share a diamond's levels).  On the benchmark grids 16
-// for the 25-point variable stencil and the variable leapfrog (32-column
-// slices, two workgroups per compute unit), 32 for the constant leapfrog.
+// constant stencil; for the 7-point variable one 10 from 256^3 points on with
+// FP32 coefficients and from 300^3 with BF16 ones, where 12 waves share a
+// diamond's nine levels (FP32: equal at 256^3, 1.17-1.25x the rate of 6 at
+// 320^3 .. 512^3; BF16: 0.87x at 256^3, 1.01-1.16x at 320^3 .. 512^3), else 6.
+// On the benchmark grids 16 for the 25-point variable stencil and the
+// variable leapfrog (32-column slices, two workgroups per compute unit), 32
+// for the constant leapfrog.
 int blocked_default_dw(int kind, int64_t points, bool bf16) {
     switch (kind) {
-    case 2: return (!bf16 && points >= 256LL * 256 * 256) ? 10 : 6;
+    case 2: return points >= (bf16 ? 300LL * 300 * 300 : 256LL * 256 * 256) ? 10 : 6;
     case 3: return 16;
     case 4: return 32;
     case 5: return 16;

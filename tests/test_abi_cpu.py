@@ -32,10 +32,12 @@ def test_default_diamond_widths():
     small, large = (64, 64, 64), (512, 512, 512)
     assert [st.default_dw(k, small) for k in (1, 2, 3, 4, 5)] == [6, 6, 16, 32, 16]
     assert [st.default_dw(k, large) for k in (1, 2, 3, 4, 5)] == [6, 10, 16, 32, 16]
-    # the 7-point variable stencil: 10 from 256^3 points on, FP32 coefficients only
+    # the 7-point variable stencil: 10 from 256^3 points on (300^3 with BF16 coefficients)
     assert st.default_dw(2, (256, 256, 256)) == 10
     assert st.default_dw(2, (255, 256, 256)) == 6
-    assert st.default_dw(2, large, "bf16") == 6
+    assert st.default_dw(2, large, "bf16") == 10
+    assert st.default_dw(2, (300, 300, 300), "bf16") == 10
+    assert st.default_dw(2, (288, 288, 288), "bf16") == 6
     assert st.default_dw(3, large, "bf16") == 16
     lib = st.load()
     assert lib.stencil_default_dw(9, 8, 8, 8, 0) == 0
