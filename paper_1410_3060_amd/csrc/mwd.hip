@@ -288,21 +288,43 @@ struct mwd_band {
         o_ht += I.sz4;
         o_fl += I.sz4;
         if constexpr (K > 0) {
-            if constexpr (C::ALN) {
-                uint32_t wv[K];
+            // The band with the LDS ring keeps them as loaded (FP32 values,
+            // BF16 words or halfwords) until they enter the ring two steps
+            // later (cbits): expanding them beside the loads makes the wave
+            // wait for the loads here.  The register-ring bands expand them
+            // at once (cexp): raw values held beside the ring cost them more
+            // registers than the wait.
 #pragma unroll
-                for (int kk = 0; kk < K; ++kk)
-                    wv[kk] = __builtin_amdgcn_raw_buffer_load_b32(I.crs(kk), o_c & ~3u, I.csoff(kk), 0);
-#pragma unroll
-                for (int kk = 0; kk < K; ++kk)
-                    p_c[SL][kk] = __uint_as_float(__builtin_amdgcn_perm(wv[kk], wv[kk], csel));
-            } else {
-#pragma unroll
-                for (int kk = 0; kk < K; ++kk)
-                    p_c[SL][kk] = cload(static_cast<const typename C::CT*>(nullptr), I.crs(kk), o_c, I.csoff(kk));
+            for (int kk = 0; kk < K; ++kk) {
+                float raw;
+                if constexpr (C::ALN)
+                    raw = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(I.crs(kk), o_c & ~3u, I.csoff(kk), 0));
+                else if constexpr (std::is_same<typename C::CT, float>::value)
+                    raw = bload(I.crs(kk), o_c, I.csoff(kk));
+                else
+                    raw = __uint_as_float(
+                        static_cast<uint32_t>(__builtin_amdgcn_raw_buffer_load_b16(I.crs(kk), o_c, I.csoff(kk), 0)));
+                p_c[SL][kk] = RL ? raw : cexp(raw);
             }
             o_c += I.szc;
         }
+    }
+
+    // a loaded coefficient as its FP32 value (BF16 expanded exactly)
+    __device__ __forceinline__ float cexp(float raw) const {
+        if constexpr (std::is_same<typename C::CT, float>::value)
+            return raw;
+        else if constexpr (C::ALN)
+            return __uint_as_float(__builtin_amdgcn_perm(__float_as_uint(raw), __float_as_uint(raw), csel));
+        else
+            return __uint_as_float(__float_as_uint(raw) << 16);
+    }
+    // a loaded BF16 coefficient's 16 stored bits (from the raw load)
+    __device__ __forceinline__ uint16_t cbits(float raw) const {
+        if constexpr (C::ALN)
+            return (uint16_t)(__float_as_uint(cexp(raw)) >> 16);
+        else
+            return (uint16_t)__float_as_uint(raw);
     }
 
     // halos of the computed levels jo+1 .. jn-1 that the staging at the end
@@ -344,7 +366,7 @@ struct mwd_band {
                     if constexpr (std::is_same<typename C::RT, float>::value)
                         I.ring0[rslot][kk][I.ringw][I.lane] = p_c[P][kk];
                     else
-                        I.ring0[rslot][kk][I.ringw][I.lane] = (uint16_t)(__float_as_uint(p_c[P][kk]) >> 16);
+                        I.ring0[rslot][kk][I.ringw][I.lane] = cbits(p_c[P][kk]);
                 }
             } else {
 #pragma unroll
