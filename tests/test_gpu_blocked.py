@@ -200,6 +200,31 @@ def test_blocked_radius4_seeded_random_cases():
         done += 1
 
 
+def test_blocked_radius1_seeded_random_cases():
+    """Seeded random configurations of the radius-1 kernel: shape (x up to 200
+    so that interior x-tiles occur beside boundary ones, y up to 60, z up to
+    90 so that the steady-state steps occur in some z-chunks and not in
+    others), nt 1..13, every provided width, FP32 or BF16 coefficients for the
+    variable stencil, padded or contiguous layout, default or forced
+    z-chunks; each bit-identical to naive."""
+    rng = np.random.default_rng([1410, 3060, 1])
+    for _ in range(24):
+        index = int(rng.choice([1, 3]))
+        dw = int(rng.choice([4, 6, 8, 10, 12]))
+        n3 = (int(rng.integers(1, 201)), int(rng.integers(1, 61)), int(rng.integers(1, 91)))
+        nt = int(rng.integers(1, 14))
+        dtype = "bf16" if index == 3 and rng.random() < 0.4 else "f32"
+        aligned = bool(rng.random() < 0.7)
+        zchunk = int(rng.choice([0, 5, 17, 40]))
+        what = (f"workload {index} dw {dw} n {n3} nt {nt} {dtype} "
+                f"{'padded' if aligned else 'contiguous'} zchunk {zchunk}")
+        print(what, flush=True)
+        wl = workloads.make(index, n=n3, nt=nt, coef_dtype=dtype)
+        nb, _ = run_gpu(wl, st.NAIVE, nt=nt, aligned=aligned)
+        bl, _ = run_gpu(wl, st.BLOCKED, nt=nt, aligned=aligned, dw=dw, zchunk=zchunk)
+        assert_bitwise(bl, nb, what)
+
+
 @pytest.mark.parametrize("index,dw,nx", [(2, 32, 1100), (4, 24, 1100), (5, 16, 2100)])
 def test_blocked_radius4_team_across_xcds(index, dw, nx):
     """A team larger than one XCD holds (33 to 69 slices against 32 or 64
